@@ -1,0 +1,196 @@
+/*
+ * chw.h -- C ABI of libchw, the Cascading Haar Wavelet (CHW) computation of
+ * the dyadic-ordered (Paley) Walsh-Hadamard transform on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * What is computed.  For every signal i of a batch, with n_i = 2^{m_i}:
+ *
+ *   orthonormal mode   y_i = H_{m_i} x_i
+ *   unnormalized mode  y_i = H'_{m_i} x_i,   H'_m = 2^{m/2} H_m  (entries +-1)
+ *
+ * where H_m is the Hadamard matrix with columns in dyadic (Paley) order of
+ * eq. (1) of the paper (H_0 = 1, H_{k+1} = 2^{-1/2}[H_k (x) (1 1); H_k (x)
+ * (1 -1)]).  It is evaluated by the CHW algorithm of Sec. 2 / Theorem 1
+ * (eq. 3): a full-size Haar transform Psi_m (eq. 2) followed by the m-1
+ * block-diagonal factors I_{r-1} (x) diag(I_{m-r}, Psi_{m-r}), with the
+ * identity blocks not performed, m*2^m additions in all (Theorem 2).  The
+ * backward call applies H_m^T as the transposed factors in reverse order.
+ * H_m is symmetric, so forward and backward give the same numbers.
+ *
+ * Memory.  All data pointers are DEVICE pointers (hipMalloc, or a torch
+ * CUDA/HIP tensor's data_ptr()).  Host pointers are named as such below.
+ * The caller owns x, y, the workspace and the stream; the plan owns copies
+ * of the sizes and offsets, its device-side work tables and any captured
+ * graph.
+ *
+ * Errors.  Every entry point returns a chw_status.  Arguments are checked
+ * before any device work is enqueued; on error nothing is written.  No entry
+ * point aborts, throws or prints (except with CHW_LOG set).  A detail string
+ * for the last failure of the calling thread is kept by chw_last_error().
+ * Calls enqueue work asynchronously on the given stream and return; device
+ * faults surface at the caller's next synchronizing HIP call.
+ */
+#ifndef CHW_H
+#define CHW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque plan handle. */
+typedef struct chw_plan_s *chw_plan_t;
+
+/* Element type of x and y.  BF16 and F16 are stored as 16-bit values and
+ * computed in FP32 inside every pass (the intermediate between HBM passes is
+ * FP32); the result is rounded to nearest even.  F64 is for verification and
+ * gradient checks. */
+typedef enum {
+    CHW_F32 = 0,
+    CHW_BF16 = 1,
+    CHW_F16 = 2,
+    CHW_I32 = 3,
+    CHW_F64 = 4
+} chw_dtype;
+
+/* CHW_ORTHONORMAL: y = H_m x (float types only).
+ * CHW_UNNORMALIZED: y = H'_m x, every 1/sqrt(2) of eqs. (1)-(2) dropped.
+ * The integer type supports only CHW_UNNORMALIZED: int32 arithmetic wraps
+ * modulo 2^32, so the result is exact whenever it fits in int32 (always the
+ * case for |x| <= 128 and n <= 2^22). */
+typedef enum {
+    CHW_ORTHONORMAL = 0,
+    CHW_UNNORMALIZED = 1
+} chw_norm;
+
+typedef enum {
+    CHW_OK = 0,
+    CHW_ERR_INVALID_ARGUMENT = 1, /* NULL/negative/out-of-range/overlapping */
+    CHW_ERR_UNSUPPORTED = 2,      /* valid request this build cannot serve  */
+    CHW_ERR_MISALIGNED = 3,       /* pointer or offset not 16-byte aligned  */
+    CHW_ERR_OUT_OF_MEMORY = 4,    /* host/device allocation or size overflow */
+    CHW_ERR_NO_DEVICE = 5,        /* no usable gfx950 device in this process */
+    CHW_ERR_HIP = 6,              /* a HIP runtime call failed              */
+    CHW_ERR_DEVICE = 7            /* a kernel reported an error flag        */
+} chw_status;
+
+/* Plan flags. */
+enum {
+    CHW_FLAG_GRAPH = 1u << 0,        /* capture the launches of a call in a
+                                        hipGraph and replay it               */
+    CHW_FLAG_NO_AUTOTUNE = 1u << 1,  /* ignore the tuning cache              */
+    CHW_FLAG_PERSISTENT = 1u << 2,   /* one persistent work-queue launch      */
+    CHW_FLAG_MULTI_LAUNCH = 1u << 3  /* one launch per HBM pass              */
+};
+
+/* Largest supported log2 signal size (all dtypes except F64). */
+#define CHW_MAX_LOG2 27
+/* Largest supported log2 signal size for CHW_F64. */
+#define CHW_MAX_LOG2_F64 20
+
+/*
+ * chw_plan -- validate a batch description and build a plan.
+ *
+ *   plan        out: the new plan (host pointer to a handle).
+ *   batch       number of signals, >= 0 (0 gives a plan whose calls do
+ *               nothing).
+ *   log2_sizes  host array [batch]: m_i, 0 <= m_i <= CHW_MAX_LOG2
+ *               (CHW_MAX_LOG2_F64 for CHW_F64).  m_i = 0 is a copy (H_0 = 1).
+ *   offsets     host array [batch + 1] of int64 ELEMENT offsets, or NULL for
+ *               signals packed back to back from element 0.  Signal i
+ *               occupies [offsets[i], offsets[i] + 2^{m_i}); offsets must be
+ *               non-negative, ascending and non-overlapping:
+ *               offsets[i] + 2^{m_i} <= offsets[i + 1].  offsets[batch] is the
+ *               extent of the buffers in elements.  Elements in gaps are never
+ *               read or written.  Signals whose byte size is >= 16 must start
+ *               on a 16-byte boundary (offsets[i] * sizeof(element) % 16 == 0)
+ *               or CHW_ERR_MISALIGNED is returned.
+ *   dtype, norm see the enums.  I32 requires CHW_UNNORMALIZED.
+ *   flags       CHW_FLAG_* bits.
+ *
+ * The plan is immutable after creation (tuning aside) and may be used from
+ * several host threads at once provided each call uses its own workspace.
+ * Planning itself needs no device; device tables are uploaded at first use
+ * on the device that is current at that time.
+ */
+chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
+                    const int64_t *offsets, chw_dtype dtype, chw_norm norm,
+                    uint32_t flags);
+
+/* Bytes of device workspace a call needs (0 when every signal fits one pass,
+ * or for out-of-place F32/I32/F64 calls, which route the intermediate through
+ * y).  The workspace holds FP32 (FP64 for CHW_F64) intermediates between HBM
+ * passes, must not be shared by concurrent calls and may be NULL when this
+ * returns 0 for the call's aliasing. */
+chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes);
+
+/*
+ * chw_forward -- y_i = H_{m_i} x_i (or H'_{m_i} x_i) for every signal.
+ *
+ *   x, y       device buffers of plan's dtype, each of extent offsets[batch]
+ *              elements; 16-byte aligned.  y == x (in place) is allowed;
+ *              partial overlap is CHW_ERR_INVALID_ARGUMENT.
+ *   workspace  device buffer of chw_workspace_size() bytes, or NULL when that
+ *              is 0 (see chw_workspace_size for out-of-place calls).
+ *   stream     a hipStream_t, or NULL for the default stream.
+ */
+chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
+                       void *stream);
+
+/* chw_backward -- y_i = H_{m_i}^T g_i: the adjoint of eq. (3), applied as the
+ * transposed factors in reverse order (Haar synthesis).  Same arguments and
+ * rules as chw_forward. */
+chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace,
+                        void *stream);
+
+/* Release a plan and its device tables and graphs.  NULL is a no-op.  The
+ * caller must have synchronized every stream the plan was used on. */
+chw_status chw_plan_destroy(chw_plan_t plan);
+
+/* Override a planner choice before first use.  Keys (value):
+ *   "split_l1"   (int) levels of the first HBM pass for multi-pass signals
+ *   "tile_log2"  (int) 12 or 15: tile size of the pass kernels
+ *   "exec"       (int) 0 = multi-launch, 1 = persistent
+ *   "grid"       (int) persistent grid size in workgroups (0 = automatic)
+ * Unknown keys or values give CHW_ERR_INVALID_ARGUMENT; a plan that has been
+ * used gives CHW_ERR_INVALID_ARGUMENT (plans are immutable once used). */
+chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value);
+
+/* Write a NUL-terminated JSON description of the plan (passes, level split,
+ * tile sizes, work items, workspace) into the host buffer buf of len bytes. */
+chw_status chw_plan_describe(chw_plan_t plan, char *buf, size_t len);
+
+/* Time the candidate configurations of this plan on the given buffers (y and
+ * workspace are overwritten; x is read only unless x == y) and keep the
+ * fastest.  `iters` timed repetitions per candidate.  Every candidate
+ * computes bitwise-identical results. */
+chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace,
+                        void *stream, int iters);
+
+/* Host-only consistency check of the tile kernels' index maps (no device
+ * needed): runs the kernels' own layout formulas on the CPU for every compiled
+ * tile shape and checks that each load/round/store phase is a bijection onto
+ * the tile, stays inside the LDS allocation, and that the per-thread base plus
+ * compile-time offset split equals the intended address.  Writes a JSON
+ * report (including worst LDS bank multiplicities per phase) into the host
+ * buffer report[len] (truncated if short; may be NULL).  Returns CHW_OK, or
+ * CHW_ERR_UNSUPPORTED when a map is inconsistent. */
+chw_status chw_layout_selfcheck(char *report, size_t len);
+
+/* Human-readable name of a status code (static storage). */
+const char *chw_status_string(chw_status s);
+
+/* Detail of the calling thread's last failed call (static or thread-local
+ * storage; "" when none). */
+const char *chw_last_error(void);
+
+/* Library version string. */
+const char *chw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHW_H */

@@ -1,0 +1,260 @@
+"""ctypes binding of libchw (argument marshalling only).
+
+Every step of the transform runs in the HIP kernels of libchw.so; this module
+only converts Python arguments to the C ABI of include/chw.h.  PyTorch is
+used for device memory (tensors) and streams.  If the shared library is not
+built, every entry point raises: there is no fallback implementation.
+"""
+
+import ctypes
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchw.so")
+
+# enums of chw.h
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "i32": 3, "f64": 4}
+NORMS = {"ortho": 0, "none": 1}
+STATUS = {0: "CHW_OK", 1: "CHW_ERR_INVALID_ARGUMENT", 2: "CHW_ERR_UNSUPPORTED",
+          3: "CHW_ERR_MISALIGNED", 4: "CHW_ERR_OUT_OF_MEMORY", 5: "CHW_ERR_NO_DEVICE",
+          6: "CHW_ERR_HIP", 7: "CHW_ERR_DEVICE"}
+FLAG_GRAPH = 1 << 0
+FLAG_NO_AUTOTUNE = 1 << 1
+FLAG_PERSISTENT = 1 << 2
+FLAG_MULTI_LAUNCH = 1 << 3
+
+# symbols declared in include/chw.h: name -> (restype, argtypes)
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "chw_plan": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
+    "chw_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "chw_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "chw_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "chw_plan_destroy": (ctypes.c_int, [_VP]),
+    "chw_plan_set_option": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_int64]),
+    "chw_plan_describe": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
+    "chw_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int]),
+    "chw_layout_selfcheck": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+    "chw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "chw_last_error": (ctypes.c_char_p, []),
+    "chw_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class CHWError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        self.name = STATUS.get(status, "CHW_ERR_%d" % status)
+        self.detail = detail
+        super().__init__("%s: %s" % (self.name, detail))
+
+
+def load():
+    """Load libchw.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libchw.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise CHWError(status, load().chw_last_error().decode())
+
+
+def version():
+    return load().chw_version().decode()
+
+
+def layout_selfcheck():
+    """(ok, report) of the host-side check of the kernels' index maps."""
+    buf = ctypes.create_string_buffer(1 << 20)
+    st = load().chw_layout_selfcheck(buf, len(buf))
+    return st == 0, json.loads(buf.value.decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+_TORCH_DT = {"f32": "float32", "bf16": "bfloat16", "f16": "float16", "i32": "int32",
+             "f64": "float64"}
+
+
+class Plan:
+    """A libchw plan for a batch of signals of sizes 2^log2_sizes[i].
+
+    offsets: None (packed back to back) or batch + 1 int64 element offsets.
+    dtype: 'f32', 'bf16', 'f16', 'i32' or 'f64'.  norm: 'ortho' or 'none'.
+    """
+
+    def __init__(self, log2_sizes, dtype="f32", norm="ortho", offsets=None, graph=False,
+                 flags=0):
+        lib = load()
+        import numpy as np
+        sizes = np.ascontiguousarray(log2_sizes, dtype=np.int32).ravel()
+        self.batch = int(sizes.size)
+        self.log2_sizes = sizes
+        self.dtype = dtype
+        self.norm = norm
+        offs_arr = None
+        if offsets is not None:
+            offs_arr = np.ascontiguousarray(offsets, dtype=np.int64).ravel()
+            if offs_arr.size != self.batch + 1:
+                raise ValueError("offsets needs batch + 1 entries")
+        self.offsets = offs_arr
+        flags = int(flags) | (FLAG_GRAPH if graph else 0)
+        h = _VP()
+        _check(lib.chw_plan(ctypes.byref(h), self.batch,
+                            sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            None if offs_arr is None else
+                            offs_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            DTYPES[dtype], NORMS[norm], flags))
+        self._h = h
+        if offs_arr is None:
+            self.extent = int(np.sum(np.left_shift(np.int64(1), sizes.astype(np.int64))))
+        else:
+            self.extent = int(offs_arr[-1])
+        self._ws = {}
+
+    # -- plan queries ---------------------------------------------------------
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        _check(load().chw_workspace_size(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(load().chw_plan_describe(self.handle, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def set_option(self, key, value):
+        _check(load().chw_plan_set_option(self.handle, key.encode(), int(value)))
+
+    # -- calls ------------------------------------------------------------------
+    def _tensor_check(self, t, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.dtype != getattr(torch, _TORCH_DT[self.dtype]):
+            raise TypeError("%s has dtype %s, plan expects %s" % (name, t.dtype, self.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if t.device.type != "cuda":
+            raise ValueError("%s must live on a GPU device" % name)
+        if t.numel() < self.extent:
+            raise ValueError("%s holds %d elements, the plan spans %d" % (name, t.numel(), self.extent))
+
+    def _workspace(self, device, needed):
+        if not needed:
+            return None
+        nbytes = self.workspace_size()
+        key = str(device)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = _torch().empty(max(nbytes, 16), dtype=_torch().uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+    def _call(self, fn, x, out, workspace, stream, adjoint):
+        torch = _torch()
+        self._tensor_check(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._tensor_check(out, "out")
+        if workspace is None:
+            narrow = self.dtype in ("bf16", "f16")
+            need = self.workspace_size() > 0 and (adjoint or narrow or
+                                                  out.data_ptr() == x.data_ptr())
+            workspace = self._workspace(x.device, need)
+        ws_ptr = None if workspace is None else workspace.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        sp = stream if isinstance(stream, int) else stream.cuda_stream
+        _check(fn(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()), _VP(ws_ptr), _VP(sp)))
+        return out
+
+    def forward(self, x, out=None, workspace=None, stream=None):
+        """out = H x for every signal (H'x in the unnormalized form)."""
+        return self._call(load().chw_forward, x, out, workspace, stream, False)
+
+    def backward(self, g, out=None, workspace=None, stream=None):
+        """out = H^T g for every signal (the reversed cascade of transposed factors)."""
+        return self._call(load().chw_backward, g, out, workspace, stream, True)
+
+    def autotune(self, x, out, workspace=None, iters=3, stream=None):
+        torch = _torch()
+        self._tensor_check(x, "input")
+        self._tensor_check(out, "out")
+        if workspace is None:
+            workspace = self._workspace(x.device, self.workspace_size() > 0)
+        ws_ptr = None if workspace is None else workspace.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(load().chw_autotune(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()),
+                                   _VP(ws_ptr), _VP(stream.cuda_stream), int(iters)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().chw_plan_destroy(self._h)
+            self._h = None
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_function():
+    torch = _torch()
+
+    class CHWFunction(torch.autograd.Function):
+        """y = H x per signal; the backward applies H^T through chw_backward."""
+
+        @staticmethod
+        def forward(ctx, x, plan):
+            ctx.plan = plan
+            return plan.forward(x.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            return ctx.plan.backward(g.contiguous()), None
+
+    return CHWFunction
+
+
+_fn_cache = None
+
+
+def chw_function():
+    """The torch.autograd.Function wrapping chw_forward / chw_backward."""
+    global _fn_cache
+    if _fn_cache is None:
+        _fn_cache = _make_function()
+    return _fn_cache
+
+
+def transform(x, plan):
+    """Differentiable y = H x (applies CHWFunction)."""
+    return chw_function().apply(x, plan)

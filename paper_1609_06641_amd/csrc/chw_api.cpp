@@ -1,0 +1,567 @@
+// chw_api.cpp -- the C ABI of libchw: validation, device state, launches,
+// hipGraph replay and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "chw.h"
+#include "chw_planner.h"
+#include "chw_types.h"
+#include "chw_variants.h"
+
+using namespace chw;
+
+namespace {
+
+thread_local std::string t_last_error;
+
+bool log_enabled()
+{
+    static const bool on = std::getenv("CHW_LOG") != nullptr;
+    return on;
+}
+
+chw_status fail(chw_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    if (log_enabled()) std::fprintf(stderr, "[libchw] %s: %s\n", chw_status_string(s), buf);
+    return s;
+}
+
+chw_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(CHW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- per-device resources of a plan -----------------------------------------
+
+struct GraphEntry {
+    int adj;
+    const void *x;
+    void *y;
+    void *ws;
+    hipGraphExec_t exec;
+};
+
+struct DeviceState {
+    int version = -1;              // plan build the tables belong to
+    Item *items = nullptr;
+    int64_t *list = nullptr;
+    int64_t *tiny_off = nullptr;
+    int32_t *tiny_m = nullptr;
+    hipStream_t cap = nullptr;     // private stream for graph capture
+    std::vector<GraphEntry> graphs;
+
+    void free_tables()
+    {
+        if (items) (void)hipFree(items);
+        if (list) (void)hipFree(list);
+        if (tiny_off) (void)hipFree(tiny_off);
+        if (tiny_m) (void)hipFree(tiny_m);
+        items = nullptr;
+        list = nullptr;
+        tiny_off = nullptr;
+        tiny_m = nullptr;
+        drop_graphs();
+    }
+    void drop_graphs()
+    {
+        for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
+};
+
+struct DeviceInfo {
+    bool ok = false;
+    std::string arch;
+    int cus = 0;
+};
+
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev_info;
+
+}  // namespace
+
+struct chw_plan_s {
+    int64_t batch = 0;
+    int dt = 0;
+    chw_norm norm = CHW_ORTHONORMAL;
+    uint32_t flags = 0;
+    std::vector<int32_t> m;
+    std::vector<int64_t> off;  // [batch]
+    int64_t extent = 0;        // elements
+    PlanConfig cfg;
+    BuiltPlan built;
+    int version = 0;
+    bool used = false;
+    std::mutex mu;
+    std::map<int, DeviceState> dev;
+};
+
+namespace {
+
+chw_status rebuild(chw_plan_t p, const PlanConfig &cfg)
+{
+    try {
+        BuiltPlan b;
+        build_plan(p->m, p->off, p->dt, cfg, &b);
+        p->built = std::move(b);
+        p->cfg = cfg;
+        ++p->version;
+    } catch (const std::bad_alloc &) {
+        return fail(CHW_ERR_OUT_OF_MEMORY, "host allocation failed while planning");
+    } catch (const std::exception &e) {
+        return fail(CHW_ERR_UNSUPPORTED, "%s", e.what());
+    }
+    return CHW_OK;
+}
+
+chw_status device_check(int *dev_out)
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(CHW_ERR_NO_DEVICE, "no HIP device visible to this process");
+    }
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev_info.find(dev);
+    if (it == g_dev_info.end()) {
+        DeviceInfo info;
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        info.arch = prop.gcnArchName;
+        info.cus = prop.multiProcessorCount;
+        info.ok = info.arch.rfind("gfx950", 0) == 0;
+        it = g_dev_info.emplace(dev, info).first;
+    }
+    if (!it->second.ok)
+        return fail(CHW_ERR_UNSUPPORTED, "device %d is %s; libchw is built for gfx950", dev,
+                    it->second.arch.c_str());
+    *dev_out = dev;
+    return CHW_OK;
+}
+
+template <typename T>
+chw_status upload(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty()) return CHW_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        (void)hipGetLastError();
+        return fail(CHW_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed", src.size() * sizeof(T));
+    }
+    e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of plan tables");
+    return CHW_OK;
+}
+
+// Caller holds p->mu.
+chw_status ensure_tables(chw_plan_t p, int dev, DeviceState **out)
+{
+    DeviceState &ds = p->dev[dev];
+    if (ds.version != p->version) {
+        ds.free_tables();
+        chw_status s;
+        if ((s = upload(&ds.items, p->built.items)) != CHW_OK) return s;
+        if ((s = upload(&ds.list, p->built.list)) != CHW_OK) return s;
+        if ((s = upload(&ds.tiny_off, p->built.tiny_off)) != CHW_OK) return s;
+        if ((s = upload(&ds.tiny_m, p->built.tiny_m)) != CHW_OK) return s;
+        ds.version = p->version;
+    }
+    *out = &ds;
+    return CHW_OK;
+}
+
+// Enqueue the launches of one call on `stream`.
+chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
+                   int inter_is_io, hipStream_t stream)
+{
+    const BuiltPlan &b = p->built;
+    LaunchArgs a{};
+    a.in = x;
+    a.out = y;
+    a.inter = inter;
+    a.inter_is_io = inter_is_io;
+    a.list = ds.list;
+    a.ortho = p->norm == CHW_ORTHONORMAL ? 1 : 0;
+    a.counters = nullptr;
+    a.spin_limit = 0;
+    if (!b.tiny_off.empty()) {
+        const TinyVariant *tv = find_tiny_variant(p->dt, adj);
+        if (!tv) return fail(CHW_ERR_UNSUPPORTED, "no tiny kernel for this dtype");
+        const int n = (int)b.tiny_off.size();
+        hipError_t e = tv->launch(dim3((n + 255) / 256), dim3(256), stream, x, y, ds.tiny_off,
+                                  ds.tiny_m, n, a.ortho);
+        if (e != hipSuccess) return hip_fail(e, "tiny kernel launch");
+    }
+    const std::vector<LaunchRange> *ph = adj ? b.adj : b.fwd;
+    for (int f = 0; f < 2; ++f)
+        for (const LaunchRange &r : ph[f]) {
+            const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
+            if (!v)
+                return fail(CHW_ERR_UNSUPPORTED, "no tile kernel for dtype %d, K=%d, LR=%d", p->dt,
+                            r.K, r.LR);
+            a.items = ds.items + r.begin;
+            a.nitems = r.end - r.begin;
+            hipError_t e = v->launch(dim3(a.nitems), stream, a);
+            if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+        }
+    return CHW_OK;
+}
+
+bool intervals_overlap(const void *a, size_t alen, const void *b, size_t blen)
+{
+    const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
+    return x < y + blen && y < x + alen;
+}
+
+chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *stream_v)
+{
+    if (!p) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (p->batch == 0 || p->extent == 0) return CHW_OK;
+    if (!x || !y) return fail(CHW_ERR_INVALID_ARGUMENT, "x and y must be device pointers");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u)
+        return fail(CHW_ERR_MISALIGNED, "x and y must be 16-byte aligned");
+    const size_t bytes = (size_t)p->extent * (size_t)elem_bytes(p->dt);
+    if (x != y && intervals_overlap(x, bytes, y, bytes))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "x and y overlap partially");
+    void *inter = nullptr;
+    int inter_is_io = 0;
+    if (p->built.ws_elems > 0) {
+        const bool narrow = p->dt == DT_BF16 || p->dt == DT_F16;
+        if (ws) {
+            if (reinterpret_cast<uintptr_t>(ws) & 15u)
+                return fail(CHW_ERR_MISALIGNED, "workspace must be 16-byte aligned");
+            const size_t wsb = p->built.ws_elems * (size_t)compute_bytes(p->dt);
+            if (intervals_overlap(ws, wsb, x, bytes))
+                return fail(CHW_ERR_INVALID_ARGUMENT, "workspace overlaps x");
+            if (intervals_overlap(ws, wsb, y, bytes))
+                return fail(CHW_ERR_INVALID_ARGUMENT, "workspace overlaps y");
+            inter = ws;
+        } else if (!adj && !narrow && x != y) {
+            inter = y;  // out-of-place forward: the intermediate goes through y
+            inter_is_io = 1;
+        } else {
+            return fail(CHW_ERR_INVALID_ARGUMENT,
+                        "this call needs a workspace of chw_workspace_size() bytes");
+        }
+    }
+    int dev = 0;
+    chw_status s = device_check(&dev);
+    if (s != CHW_OK) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->used = true;
+    DeviceState *ds = nullptr;
+    if ((s = ensure_tables(p, dev, &ds)) != CHW_OK) return s;
+    if (!(p->flags & CHW_FLAG_GRAPH)) return enqueue(p, *ds, adj, x, y, inter, inter_is_io, stream);
+
+    // graph replay: capture once per (direction, buffers) on a private stream
+    GraphEntry *ge = nullptr;
+    for (GraphEntry &g : ds->graphs)
+        if (g.adj == adj && g.x == x && g.y == y && g.ws == ws) ge = &g;
+    if (!ge) {
+        hipError_t e;
+        if (!ds->cap) {
+            e = hipStreamCreateWithFlags(&ds->cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        }
+        if (ds->graphs.size() >= 16) {
+            (void)hipGraphExecDestroy(ds->graphs.front().exec);
+            ds->graphs.erase(ds->graphs.begin());
+        }
+        e = hipStreamBeginCapture(ds->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        chw_status es = enqueue(p, *ds, adj, x, y, inter, inter_is_io, ds->cap);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(ds->cap, &graph);
+        if (es != CHW_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return es;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        ds->graphs.push_back(GraphEntry{adj, x, y, ws, exec});
+        ge = &ds->graphs.back();
+    }
+    hipError_t e = hipGraphLaunch(ge->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return CHW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *chw_status_string(chw_status s)
+{
+    switch (s) {
+    case CHW_OK: return "CHW_OK";
+    case CHW_ERR_INVALID_ARGUMENT: return "CHW_ERR_INVALID_ARGUMENT";
+    case CHW_ERR_UNSUPPORTED: return "CHW_ERR_UNSUPPORTED";
+    case CHW_ERR_MISALIGNED: return "CHW_ERR_MISALIGNED";
+    case CHW_ERR_OUT_OF_MEMORY: return "CHW_ERR_OUT_OF_MEMORY";
+    case CHW_ERR_NO_DEVICE: return "CHW_ERR_NO_DEVICE";
+    case CHW_ERR_HIP: return "CHW_ERR_HIP";
+    case CHW_ERR_DEVICE: return "CHW_ERR_DEVICE";
+    }
+    return "CHW_ERR_UNKNOWN";
+}
+
+const char *chw_last_error(void) { return t_last_error.c_str(); }
+
+const char *chw_version(void) { return "libchw 0.1 (gfx950)"; }
+
+chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
+                    const int64_t *offsets, chw_dtype dtype, chw_norm norm, uint32_t flags)
+{
+    t_last_error.clear();
+    if (!plan) return fail(CHW_ERR_INVALID_ARGUMENT, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (batch < 0) return fail(CHW_ERR_INVALID_ARGUMENT, "batch %lld < 0", (long long)batch);
+    if (batch > 0 && !log2_sizes) return fail(CHW_ERR_INVALID_ARGUMENT, "log2_sizes is NULL");
+    if ((int)dtype < 0 || (int)dtype > 4) return fail(CHW_ERR_INVALID_ARGUMENT, "bad dtype %d", (int)dtype);
+    if ((int)norm < 0 || (int)norm > 1) return fail(CHW_ERR_INVALID_ARGUMENT, "bad norm %d", (int)norm);
+    if (dtype == CHW_I32 && norm != CHW_UNNORMALIZED)
+        return fail(CHW_ERR_UNSUPPORTED, "the integer type has only the unnormalized form");
+    const uint32_t known = CHW_FLAG_GRAPH | CHW_FLAG_NO_AUTOTUNE | CHW_FLAG_PERSISTENT |
+                           CHW_FLAG_MULTI_LAUNCH;
+    if (flags & ~known) return fail(CHW_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", flags & ~known);
+    if ((flags & CHW_FLAG_PERSISTENT) && (flags & CHW_FLAG_MULTI_LAUNCH))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "PERSISTENT and MULTI_LAUNCH are exclusive");
+    const int dt = (int)dtype;
+    const int maxm = dtype == CHW_F64 ? CHW_MAX_LOG2_F64 : CHW_MAX_LOG2;
+    const int es = elem_bytes(dt);
+    chw_plan_s *p = nullptr;
+    try {
+        p = new chw_plan_s();
+        p->batch = batch;
+        p->dt = dt;
+        p->norm = norm;
+        p->flags = flags;
+        p->m.assign(log2_sizes, log2_sizes + batch);
+        p->off.resize((size_t)batch);
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(CHW_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    auto bad = [&](chw_status s) {
+        delete p;
+        return s;
+    };
+    int64_t pos = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        const int m = log2_sizes[i];
+        if (m < 0 || m > 30)
+            return bad(fail(CHW_ERR_INVALID_ARGUMENT, "log2_sizes[%lld] = %d outside [0, 30]",
+                            (long long)i, m));
+        if (m > maxm)
+            return bad(fail(CHW_ERR_UNSUPPORTED, "log2_sizes[%lld] = %d exceeds %d for this dtype",
+                            (long long)i, m, maxm));
+        const int64_t n = (int64_t)1 << m;
+        int64_t o;
+        if (offsets) {
+            o = offsets[i];
+            if (o < 0 || o < pos)
+                return bad(fail(CHW_ERR_INVALID_ARGUMENT,
+                                "offsets[%lld] = %lld is negative or overlaps the previous signal",
+                                (long long)i, (long long)o));
+            if (o > (((int64_t)1 << 62) - n))
+                return bad(fail(CHW_ERR_OUT_OF_MEMORY, "offsets[%lld] overflows", (long long)i));
+        } else {
+            o = pos;
+            if (o > (((int64_t)1 << 62) - n))
+                return bad(fail(CHW_ERR_OUT_OF_MEMORY, "packed batch overflows"));
+        }
+        if (n * es >= 16 && ((o * es) & 15))
+            return bad(fail(CHW_ERR_MISALIGNED, "signal %lld starts at element %lld, not 16-byte aligned",
+                            (long long)i, (long long)o));
+        p->off[(size_t)i] = o;
+        pos = o + n;
+    }
+    if (offsets) {
+        if (offsets[batch] < pos)
+            return bad(fail(CHW_ERR_INVALID_ARGUMENT, "offsets[batch] = %lld is below the end of the last signal",
+                            (long long)offsets[batch]));
+        p->extent = offsets[batch];
+    } else {
+        p->extent = pos;
+    }
+    if (p->extent > (((int64_t)1 << 62) / 8)) return bad(fail(CHW_ERR_OUT_OF_MEMORY, "extent overflows"));
+    PlanConfig cfg;
+    chw_status s = rebuild(p, cfg);
+    if (s != CHW_OK) return bad(s);
+    *plan = p;
+    return CHW_OK;
+}
+
+chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
+    *bytes = plan->built.ws_elems * (size_t)compute_bytes(plan->dt);
+    return CHW_OK;
+}
+
+chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace, void *stream)
+{
+    return run(plan, 0, x, y, workspace, stream);
+}
+
+chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace, void *stream)
+{
+    return run(plan, 1, g, y, workspace, stream);
+}
+
+chw_status chw_plan_destroy(chw_plan_t plan)
+{
+    if (!plan) return CHW_OK;
+    {
+        std::lock_guard<std::mutex> lk(plan->mu);
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        for (auto &kv : plan->dev) {
+            if (kv.first != cur) (void)hipSetDevice(kv.first);
+            kv.second.free_tables();
+            if (kv.second.cap) (void)hipStreamDestroy(kv.second.cap);
+        }
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
+    delete plan;
+    return CHW_OK;
+}
+
+chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
+{
+    if (!plan || !key) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    if (plan->used) return fail(CHW_ERR_INVALID_ARGUMENT, "plan already used; options are fixed");
+    PlanConfig cfg = plan->cfg;
+    const std::string k = key;
+    if (k == "lr12" && (value == 5 || value == 6)) cfg.lr12 = (int)value;
+    else if (k == "lr15" && (value == 5 || value == 6)) cfg.lr15 = (int)value;
+    else if (k == "single15" && (value == 0 || value == 1)) cfg.single15 = (int)value;
+    else if (k == "split_l1" && value >= -1 && value <= 30) cfg.split_l1 = (int)value;
+    else if (k == "exec" && value == 0) cfg.exec = (int)value;
+    else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
+    return rebuild(plan, cfg);
+}
+
+chw_status chw_plan_describe(chw_plan_t plan, char *buf, size_t len)
+{
+    if (!plan || !buf || len == 0) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    char head[256];
+    std::snprintf(head, sizeof head, "{\"batch\": %lld, \"dtype\": %d, \"norm\": %d, \"extent\": %lld, \"plan\": ",
+                  (long long)plan->batch, plan->dt, (int)plan->norm, (long long)plan->extent);
+    std::string s = head + describe_plan(plan->built) + "}";
+    if (s.size() + 1 > len) return fail(CHW_ERR_INVALID_ARGUMENT, "buffer of %zu bytes too small (%zu needed)", len, s.size() + 1);
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return CHW_OK;
+}
+
+chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace, void *stream,
+                        int iters)
+{
+    if (!plan) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (iters < 1) return fail(CHW_ERR_INVALID_ARGUMENT, "iters must be >= 1");
+    if (plan->batch == 0 || plan->extent == 0) return CHW_OK;
+    int dev = 0;
+    chw_status s = device_check(&dev);
+    if (s != CHW_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // candidate configurations
+    std::vector<PlanConfig> cands;
+    bool has15 = false, has_multi = false;
+    int maxm = 0;
+    for (int32_t m : plan->m) {
+        if (m >= 13 && m <= 15) has15 = true;
+        if (m > 15) has_multi = true;
+        maxm = std::max(maxm, (int)m);
+    }
+    std::vector<int> l1s = {-1};
+    if (has_multi)
+        for (int l1 : {8, 9, 10, 12}) {
+            Split sp;
+            bool ok = true;
+            for (int32_t m : plan->m)
+                if (m > 15 && !choose_split(m, plan->dt, l1, &sp)) ok = false;
+            if (ok) l1s.push_back(l1);
+        }
+    for (int lr12 : {5, 6})
+        for (int lr15 : {5, 6})
+            for (int s15 : {0, 1}) {
+                if (!has15 && s15 == 0) continue;
+                if (plan->dt == DT_F64 && (lr12 != 5 || lr15 != 5 || s15 != 1)) continue;
+                for (int l1 : l1s) {
+                    PlanConfig c;
+                    c.lr12 = lr12;
+                    c.lr15 = lr15;
+                    c.single15 = s15;
+                    c.split_l1 = l1;
+                    cands.push_back(c);
+                }
+            }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(CHW_ERR_HIP, "hipEventCreate failed");
+    const PlanConfig saved = plan->cfg;
+    float best_ms = 1e30f;
+    PlanConfig best = saved;
+    const bool was_used = plan->used;
+    for (const PlanConfig &c : cands) {
+        {
+            std::lock_guard<std::mutex> lk(plan->mu);
+            if ((s = rebuild(plan, c)) != CHW_OK) continue;
+        }
+        if ((s = run(plan, 0, x, y, workspace, stream)) != CHW_OK) break;  // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) { s = fail(CHW_ERR_HIP, "hipEventRecord"); break; }
+        for (int i = 0; i < iters && s == CHW_OK; ++i) s = run(plan, 0, x, y, workspace, stream);
+        if (s != CHW_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            s = fail(CHW_ERR_HIP, "event timing failed");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (log_enabled())
+            std::fprintf(stderr, "[libchw] tune lr12=%d lr15=%d single15=%d split_l1=%d: %.4f ms\n",
+                         c.lr12, c.lr15, c.single15, c.split_l1, ms / iters);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(plan->mu);
+    chw_status s2 = rebuild(plan, s == CHW_OK ? best : saved);
+    plan->used = was_used || s == CHW_OK;
+    return s != CHW_OK ? s : s2;
+}
+
+}  // extern "C"

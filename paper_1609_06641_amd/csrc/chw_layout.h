@@ -1,0 +1,111 @@
+// chw_layout.h -- index maps of the CHW tile engine (host and device).
+//
+// A tile is N = 2^K elements held in LDS as the compute type (FP32, int32 or
+// FP64), at padded word address pad(e) = e + (e >> LR), e = tile element.  A
+// workgroup of NT = 2^(K-LR) threads processes it; in each "round" a thread
+// holds R = 2^LR elements in registers.
+//
+// Stage t of the cascade is the set of Haar levels at depth t: after stages
+// 0..t-1 every element has been combined over input index bits 0..t-1, and
+// stage t pairs the elements that differ in bit t (the element with the bit
+// clear takes the sum, the other the difference), exactly the butterflies the
+// Haar transforms of Sec. 2 / Theorem 1 perform at that depth.  Stages run
+// in increasing t (forward) or decreasing t (adjoint).  Inside a tile, tile
+// bit b is signal bit b (single-pass tiles, first-pass rows) or signal bit
+// L1 + b (last-pass blocks).
+//
+// Every map below is a bit permutation of (thread, register/vector, unrolled
+// iteration) fields that occupy disjoint bits, so
+//     pad(a | b) = pad(a) + pad(b)   for disjoint a, b
+// and each LDS access is one per-thread base plus a compile-time offset.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__) || defined(__HIP__)
+#define CHW_HD __host__ __device__ __forceinline__
+#else
+#define CHW_HD inline
+#endif
+
+namespace chw {
+
+constexpr uint32_t cbrev(uint32_t v, int bits)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < bits; ++i) r = (r << 1) | ((v >> i) & 1u);
+    return r;
+}
+
+CHW_HD uint32_t rbrev(uint32_t v, int bits)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return bits ? (__builtin_bitreverse32(v) >> (32 - bits)) : 0u;
+#else
+    return cbrev(v, bits);
+#endif
+}
+
+template <int K_, int LR_>
+struct Layout {
+    static constexpr int K = K_, LR = LR_;
+    static constexpr int N = 1 << K, R = 1 << LR;
+    static constexpr int LNT = K - LR, NT = 1 << LNT;
+    static constexpr int J = (K + LR - 1) / LR;          // register rounds
+    static constexpr int LDS_WORDS = N + (N >> LR);
+    static_assert(LR >= 3 && LNT >= 6, "tile needs >= 8 registers and >= 1 wave");
+
+    static CHW_HD constexpr int pad(int e) { return e + (e >> LR); }
+
+    // ---- register rounds -------------------------------------------------
+    // Round j makes active the tile bits [alo(j), ahi(j)); the register field
+    // is [flo(j), flo(j) + LR) (the last round's field is moved down so that it
+    // stays inside the tile and holds R elements).
+    static CHW_HD constexpr int alo(int j) { return j * LR; }
+    static CHW_HD constexpr int ahi(int j) { return (j + 1) * LR < K ? (j + 1) * LR : K; }
+    static CHW_HD constexpr int flo(int j) { return j * LR < K - LR ? j * LR : K - LR; }
+    // tile element of (thread t, register 0) in round j: thread bits fill the
+    // tile bits outside the register field, low to high
+    static CHW_HD constexpr int round_tbase(int j, int t)
+    {
+        return (t & ((1 << flo(j)) - 1)) | ((t >> flo(j)) << (flo(j) + LR));
+    }
+    static CHW_HD constexpr int round_reg(int j, int i) { return i << flo(j); }
+
+    // ---- contiguous phase (16-byte vectors of V elements) -----------------
+    // vector q = t + NT*k covers tile elements [q*V, q*V + V)
+    template <int V>
+    static CHW_HD constexpr int contig_e(int t, int k, int u) { return V * t + V * NT * k + u; }
+
+    // ---- bit-reversed phase: output position o = (blk << bits) | p holds
+    // tile element (blk << bits) | bitrev_bits(p) ----------------------------
+    template <int V>
+    static CHW_HD int bitrev_e(int t, int k, int u, int bits)
+    {
+        int o = V * t + V * NT * k + u;
+        int blk = o >> bits;
+        int p = o & ((1 << bits) - 1);
+        return (blk << bits) | (int)rbrev((uint32_t)p, bits);
+    }
+
+    // ---- transposed phase of a first-pass tile: 2^C rows of 2^L1 elements,
+    // tile element e = (hl << L1) | lo; output o (within the tile) = (rho << C)
+    // | hl where rho = bitrev_L1(lo) indexes the output run of 2^C elements ---
+    template <int V, int C>
+    static CHW_HD int transp_e(int t, int k, int u)
+    {
+        constexpr int L1 = K - C;
+        int o = V * t + V * NT * k + u;
+        int hl = o & ((1 << C) - 1);
+        int rho = o >> C;
+        return (hl << L1) | (int)rbrev((uint32_t)rho, L1);
+    }
+    // element offset (relative to the signal base + h0) of output o, given the
+    // run stride 2^rs of the transposed layout
+    template <int C>
+    static CHW_HD int64_t transp_goff(int o, int rs)
+    {
+        return ((int64_t)(o >> C) << rs) + (o & ((1 << C) - 1));
+    }
+};
+
+}  // namespace chw

@@ -1,0 +1,247 @@
+// chw_planner.cpp -- host planner for the CHW tile kernels.
+//
+// Signals are classified by size:
+//   * tiny   : fewer bytes than one 16-byte vector -> one thread per signal;
+//   * single : 2^m fits one tile (m <= 12 in 2^12-element tiles, 13..15 in
+//              2^15-element tiles) -> one pass, 2^(K-m) signals per tile;
+//   * multi  : two HBM passes split along the level structure of the cascade.
+//              The proof of Theorem 1 (Sec. 5) shows that after the first
+//              level the rest is I_1 (x) CHW_{m-1} on the two halves; applied
+//              L1 times, the first pass runs stages 0..L1-1 on contiguous rows
+//              of 2^L1 elements and leaves 2^L1 independent contiguous blocks
+//              of 2^(m-L1) elements, on each of which the second pass runs the
+//              whole CHW_{m-L1}.
+#include "chw_planner.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <stdexcept>
+
+namespace chw {
+
+int elem_bytes(int dt)
+{
+    switch (dt) {
+    case DT_F32: case DT_I32: return 4;
+    case DT_BF16: case DT_F16: return 2;
+    case DT_F64: return 8;
+    default: return 0;
+    }
+}
+
+int compute_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
+
+bool choose_split(int m, int dt, int forced_l1, Split *out)
+{
+    struct Opt { int K1, CC, kind; };
+    const Opt opts[] = {{12, K12_CA, KIND_FIRST_A}, {15, K15_CA, KIND_FIRST_A},
+                        {12, K12_CB, KIND_FIRST_B}, {15, K15_CB, KIND_FIRST_B}};
+    const int kmax2 = dt == DT_F64 ? 12 : 15;
+    for (const Opt &o : opts) {
+        if (o.K1 == 15 && dt == DT_F64) continue;
+        const int L1 = o.K1 - o.CC;
+        if (forced_l1 > 0 && L1 != forced_l1) continue;
+        const int b = m - L1;                 // levels left for the second pass
+        if (b < o.CC || b > kmax2) continue;  // each first-pass tile needs 2^CC rows
+        out->m = m;
+        out->L1 = L1;
+        out->K1 = o.K1;
+        out->CC = o.CC;
+        out->kind = o.kind;
+        out->K2 = b <= 12 ? 12 : 15;
+        return true;
+    }
+    return false;
+}
+
+namespace {
+
+Item blank_item()
+{
+    Item it{};
+    it.list = -1;
+    it.wait_idx = -1;
+    it.done_idx = -1;
+    it.count = 1;
+    return it;
+}
+
+int tiny_max_log2(int dt)
+{
+    // fewer bytes than one 16-byte vector
+    int m = 0;
+    while (((int64_t)1 << (m + 1)) * elem_bytes(dt) < 16) ++m;
+    return m;  // F32: 1, BF16: 2, F64: 0
+}
+
+}  // namespace
+
+void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off, int dt,
+                const PlanConfig &cfg, BuiltPlan *out)
+{
+    BuiltPlan p;
+    p.cfg = cfg;
+    if (dt == DT_F64) {  // FP64 has only the 2^12-element, 32-register tile kernels
+        p.cfg.lr12 = 5;
+        p.cfg.single15 = 0;
+    }
+    const int64_t batch = (int64_t)ms.size();
+    const int tiny_max = tiny_max_log2(dt);
+    const int single_max = p.cfg.single15 ? 15 : 12;
+
+    // per (K, category) item lists; category 0 BLOCKS, 1 FIRST, 2 LAST
+    std::vector<Item> cat[2][3];
+    auto kidx = [](int K) { return K == 12 ? 0 : 1; };
+
+    // ---- single-pass signals, grouped by size ---------------------------
+    std::vector<int64_t> order;
+    order.reserve(batch);
+    for (int64_t i = 0; i < batch; ++i) {
+        const int m = ms[i];
+        if (m <= tiny_max) {
+            p.tiny_off.push_back(off[i]);
+            p.tiny_m.push_back(m);
+            ++p.n_tiny;
+        } else if (m <= single_max) {
+            order.push_back(i);
+            ++p.n_single;
+        }
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return ms[a] < ms[b]; });
+    for (size_t s = 0; s < order.size();) {
+        const int m = ms[order[s]];
+        const int K = m <= 12 ? 12 : 15;
+        const int per = 1 << (K - m);
+        size_t e = s;
+        while (e < order.size() && ms[order[e]] == m && (int)(e - s) < per) ++e;
+        Item it = blank_item();
+        it.kind = KIND_BLOCKS;
+        it.bits = m;
+        it.m = m;
+        it.count = (int32_t)(e - s);
+        bool consecutive = true;
+        for (size_t q = s + 1; q < e; ++q)
+            if (off[order[q]] != off[order[s]] + ((int64_t)(q - s) << m)) consecutive = false;
+        it.io_off = off[order[s]];
+        if (!consecutive) {
+            it.list = (int32_t)p.list.size();
+            for (size_t q = s; q < e; ++q) p.list.push_back(off[order[q]]);
+        }
+        cat[kidx(K)][0].push_back(it);
+        s = e;
+    }
+
+    // ---- multi-pass signals --------------------------------------------------
+    int64_t wsb = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        const int m = ms[i];
+        if (m <= single_max) continue;
+        Split sp;
+        if (!choose_split(m, dt, p.cfg.split_l1, &sp))
+            throw std::invalid_argument("no two-pass split covers log2 size " +
+                                        std::to_string(m));
+        ++p.n_multi;
+        bool seen = false;
+        for (const Split &q : p.splits)
+            if (q.m == sp.m && q.L1 == sp.L1 && q.K1 == sp.K1 && q.K2 == sp.K2) seen = true;
+        if (!seen) p.splits.push_back(sp);
+        const int L1 = sp.L1, b = m - L1;
+        const int64_t rows = (int64_t)1 << b;
+        for (int64_t h0 = 0; h0 < rows; h0 += (int64_t)1 << sp.CC) {
+            Item it = blank_item();
+            it.kind = sp.kind;
+            it.bits = L1;
+            it.m = m;
+            it.rs = b;
+            it.h0 = (int32_t)h0;
+            it.io_off = off[i] + (h0 << L1);
+            it.ws_off = wsb;
+            cat[kidx(sp.K1)][1].push_back(it);
+        }
+        const int bpt = 1 << (sp.K2 - b);  // blocks per last-pass tile
+        const int64_t tiles = ((int64_t)1 << L1) / bpt;
+        for (int64_t tl = 0; tl < tiles; ++tl) {
+            Item it = blank_item();
+            it.kind = KIND_LAST;
+            it.bits = b;
+            it.m = m;
+            it.count = bpt;
+            it.io_off = off[i] + (tl << sp.K2);
+            it.ws_off = wsb + (tl << sp.K2);
+            cat[kidx(sp.K2)][2].push_back(it);
+        }
+        wsb += (int64_t)1 << m;
+    }
+    p.ws_elems = (size_t)wsb;
+
+    // ---- table order: K12 {BLOCKS, FIRST, LAST}, K15 {BLOCKS, FIRST, LAST} ---
+    int start[2][3], stop[2][3];
+    for (int k = 0; k < 2; ++k)
+        for (int c = 0; c < 3; ++c) {
+            start[k][c] = (int)p.items.size();
+            p.items.insert(p.items.end(), cat[k][c].begin(), cat[k][c].end());
+            stop[k][c] = (int)p.items.size();
+        }
+    if (p.items.size() > (size_t)0x7fffffff) throw std::bad_alloc();
+    auto add = [&](std::vector<LaunchRange> &v, int k, int b, int e) {
+        if (e > b) {
+            const int K = k == 0 ? 12 : 15;
+            v.push_back(LaunchRange{K, K == 12 ? p.cfg.lr12 : p.cfg.lr15, b, e});
+        }
+    };
+    for (int k = 0; k < 2; ++k) {
+        add(p.fwd[0], k, start[k][0], stop[k][1]);   // BLOCKS + FIRST
+        add(p.fwd[1], k, start[k][2], stop[k][2]);   // LAST
+        add(p.adj[0], k, start[k][0], stop[k][0]);   // BLOCKS
+        add(p.adj[0], k, start[k][2], stop[k][2]);   // LAST (adjoint first pass)
+        add(p.adj[1], k, start[k][1], stop[k][1]);   // FIRST (adjoint second pass)
+    }
+    *out = std::move(p);
+}
+
+std::string describe_plan(const BuiltPlan &p)
+{
+    std::string s = "{";
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "\"items\": %zu, \"list\": %zu, \"tiny\": %lld, \"single\": %lld, "
+                  "\"multi\": %lld, \"ws_elems\": %zu, ",
+                  p.items.size(), p.list.size(), (long long)p.n_tiny, (long long)p.n_single,
+                  (long long)p.n_multi, p.ws_elems);
+    s += buf;
+    std::snprintf(buf, sizeof buf,
+                  "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
+                  "\"exec\": %d}, ",
+                  p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec);
+    s += buf;
+    s += "\"splits\": [";
+    for (size_t i = 0; i < p.splits.size(); ++i) {
+        const Split &q = p.splits[i];
+        std::snprintf(buf, sizeof buf, "%s{\"m\": %d, \"L1\": %d, \"K1\": %d, \"rows_log2\": %d, \"K2\": %d}",
+                      i ? ", " : "", q.m, q.L1, q.K1, q.CC, q.K2);
+        s += buf;
+    }
+    s += "], ";
+    auto ranges = [&](const char *name, const std::vector<LaunchRange> *ph) {
+        s += "\"";
+        s += name;
+        s += "\": [";
+        bool first = true;
+        for (int f = 0; f < 2; ++f)
+            for (const LaunchRange &r : ph[f]) {
+                std::snprintf(buf, sizeof buf, "%s{\"phase\": %d, \"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d}",
+                              first ? "" : ", ", f, r.K, r.LR, r.begin, r.end);
+                s += buf;
+                first = false;
+            }
+        s += "]";
+    };
+    ranges("forward", p.fwd);
+    s += ", ";
+    ranges("backward", p.adj);
+    s += "}";
+    return s;
+}
+
+}  // namespace chw

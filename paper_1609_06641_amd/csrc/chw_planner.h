@@ -1,0 +1,69 @@
+// chw_planner.h -- host planner: turns a batch description into work items
+// and launch ranges for the tile kernels (no device needed).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "chw_types.h"
+
+namespace chw {
+
+// Tunable choices.  Every choice computes bitwise-identical results: the
+// stages always run in the same order with the same operands, and the scale is
+// applied once at the final store.
+struct PlanConfig {
+    int lr12 = 6;       // register bits of the 2^12-element tile kernels (5, 6)
+    int lr15 = 5;       // register bits of the 2^15-element tile kernels (5, 6)
+    int single15 = 1;   // signals with 13 <= m <= 15 in one pass of a 2^15 tile
+    int split_l1 = -1;  // forced first-pass level count of multi-pass signals
+    int exec = 0;       // 0 = one launch per pass
+};
+
+// Items [begin, end) of the plan's table run in one launch of the tile kernel
+// with tile bits K and register bits LR.
+struct LaunchRange {
+    int K, LR;
+    int begin, end;
+};
+
+// Two-pass split of one signal size.
+struct Split {
+    int m, L1, K1, CC, kind, K2;
+};
+
+struct BuiltPlan {
+    PlanConfig cfg;
+    std::vector<Item> items;
+    std::vector<int64_t> list;        // block offsets of ragged BLOCKS items
+    std::vector<int64_t> tiny_off;    // signals below one 16-byte vector
+    std::vector<int32_t> tiny_m;
+    std::vector<LaunchRange> fwd[2];  // per phase (phase 1 waits for phase 0)
+    std::vector<LaunchRange> adj[2];
+    std::vector<Split> splits;        // distinct splits in use
+    size_t ws_elems = 0;              // compact intermediate (compute type)
+    int64_t n_single = 0, n_multi = 0, n_tiny = 0;
+};
+
+// Row counts (log2) of the first-pass variants compiled for each tile size.
+constexpr int K12_CA = 4, K12_CB = 3, K15_CA = 5, K15_CB = 3;
+
+// Storage / compute element sizes of a dtype.
+int elem_bytes(int dt);
+int compute_bytes(int dt);
+
+// Choose the two-pass split for a signal of 2^m elements; false when none of
+// the compiled variants covers m.
+bool choose_split(int m, int dt, int forced_l1, Split *out);
+
+// Build items and launch ranges.  Throws std::bad_alloc on allocation failure,
+// std::invalid_argument when a signal cannot be planned.
+void build_plan(const std::vector<int32_t> &m, const std::vector<int64_t> &off, int dt,
+                const PlanConfig &cfg, BuiltPlan *out);
+
+// JSON description of a built plan.
+std::string describe_plan(const BuiltPlan &p);
+
+}  // namespace chw

@@ -1,0 +1,77 @@
+// chw_types.h -- plain structs shared by the host planner and the kernels.
+#pragma once
+#include <stdint.h>
+
+namespace chw {
+
+enum DType : int { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2, DT_I32 = 3, DT_F64 = 4 };
+
+// Work item kinds.  A work item is one tile (one workgroup's worth of work).
+enum ItemKind : int32_t {
+    // Whole signals (or last-pass blocks) of 2^bits <= 2^K elements, 2^(K-bits)
+    // of them per tile: all stages of the block, Paley-ordered store.
+    KIND_BLOCKS = 0,
+    // First HBM pass of a large signal with the tile's variant-A row count:
+    // 2^CA rows of 2^(K-CA) contiguous elements, stages 0..K-CA-1, stored in
+    // the cascade's own layout after those stages (transposed, FP32/compute
+    // type intermediate).
+    KIND_FIRST_A = 1,
+    // Same with the variant-B row count 2^CB.
+    KIND_FIRST_B = 2,
+    // Last HBM pass: blocks of 2^bits contiguous intermediate elements (the
+    // remaining CHW_{m-L1} on each block), Paley-ordered store.
+    KIND_LAST = 3,
+};
+
+// 64-byte work item.  Offsets are element offsets:
+//   io_off : start of the tile's contiguous chunk in x / g / y space
+//            (BLOCKS, LAST: the blocks; FIRST: rows h0 .. h0 + 2^C - 1)
+//   ws_off : BLOCKS: unused; FIRST: base of the signal in the intermediate
+//            buffer; LAST: start of the tile's blocks in the intermediate.
+// Roles by direction:
+//   forward  BLOCKS : x[io] -> y[io]                (all stages, Paley store)
+//            FIRST  : x[io] -> inter[ws] transposed (stages 0..L1-1)
+//            LAST   : inter[ws] -> y[io]            (stages L1..m-1, Paley)
+//   adjoint  BLOCKS : g[io] -> y[io]                (Paley gather, stages down)
+//            LAST   : g[io] -> inter[ws]            (Paley gather, top stages)
+//            FIRST  : inter[ws] transposed -> y[io] (stages L1-1..0)
+// When the intermediate is y itself (out-of-place forward, no workspace) the
+// kernel derives its offsets from io_off instead of ws_off.
+// For BLOCKS items with list >= 0 the blocks are not consecutive: block i of
+// the tile starts at element list_base[list + i] of x and y alike.
+struct Item {
+    int64_t io_off;
+    int64_t ws_off;
+    int32_t kind;
+    int32_t bits;       // BLOCKS/LAST: log2 block size (stage bits per block)
+    int32_t count;      // BLOCKS/LAST: valid blocks in the tile (>= 1)
+    int32_t list;       // BLOCKS: index into the block-offset list, or -1
+    int32_t rs;         // FIRST: log2 stride of the transposed runs (m - L1)
+    int32_t h0;         // FIRST: first row (of 2^L1 elements) of the tile
+    int32_t m;          // log2 size of the whole signal (sets the scale)
+    int32_t wait_idx;   // persistent: counter to wait on, or -1
+    int32_t wait_target;// persistent: value the counter must reach
+    int32_t done_idx;   // persistent: counter to bump when done, or -1
+    int32_t pad_[2];
+};
+static_assert(sizeof(Item) == 64, "Item must stay 64 bytes");
+
+// Arguments of one launch of the item kernels.
+struct LaunchArgs {
+    const void *in;          // x (forward) or g (adjoint)
+    void *out;               // y
+    void *inter;             // intermediate between passes (workspace or y)
+    int32_t inter_is_io;     // 1: inter == y, offsets follow io_off
+    int32_t pad2;
+    const Item *items;       // device array
+    const int64_t *list;     // device array of block offsets (ragged BLOCKS)
+    int32_t nitems;
+    int32_t ortho;           // 1: scale by 2^{-m/2} at the final store
+    // persistent scheduling
+    int32_t *counters;       // device: [0] = work head, [1] = error flag,
+                             //         [2 + i] = per-item dependency counters
+    int32_t spin_limit;      // bounded wait (iterations of ~1us) before error
+    int32_t pad1;
+};
+
+}  // namespace chw

@@ -1,0 +1,39 @@
+// chw_variants.h -- registry of compiled kernel variants (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chw_types.h"
+
+namespace chw {
+
+typedef hipError_t (*ItemsLauncher)(dim3 grid, hipStream_t s, const LaunchArgs &a);
+typedef hipError_t (*TinyLauncher)(dim3 grid, dim3 block, hipStream_t s, const void *in,
+                                   void *out, const int64_t *offs, const int32_t *ms,
+                                   int n, int ortho);
+
+// One compiled tile kernel: dtype, tile bits K, register bits LR, the two
+// first-pass row counts (log2) CA and CB, direction.
+struct ItemsVariant {
+    int dt, K, LR, CA, CB, adj;
+    int nt;                 // threads per workgroup
+    size_t lds_bytes;       // static LDS
+    ItemsLauncher launch;
+    const void *fn;         // kernel symbol (occupancy queries)
+};
+
+struct TinyVariant {
+    int dt, adj;
+    TinyLauncher launch;
+};
+
+// All variants of all dtypes.
+const ItemsVariant *items_variants(int *count);
+const TinyVariant *tiny_variants(int *count);
+const ItemsVariant *find_items_variant(int dt, int K, int LR, int adj);
+const TinyVariant *find_tiny_variant(int dt, int adj);
+
+// Largest log2 size a tiny (one thread per signal) launch handles.
+constexpr int TINY_MAX_LOG2 = 3;
+
+}  // namespace chw

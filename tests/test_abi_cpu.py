@@ -1,0 +1,185 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments, plans (host logic) and reports the
+no-device case."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1609_06641_amd import chw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "chw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chw_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = chw.load()
+    names = _header_functions()
+    assert "chw_plan" in names and "chw_forward" in names and "chw_backward" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(chw.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_status_strings():
+    lib = chw.load()
+    assert chw.version().startswith("libchw")
+    for code, name in chw.STATUS.items():
+        assert lib.chw_status_string(code).decode() == name
+
+
+def _plan_raw(sizes, offsets=None, dtype=0, norm=0, flags=0, batch=None):
+    lib = chw.load()
+    h = ctypes.c_void_p()
+    s = None if sizes is None else np.ascontiguousarray(sizes, dtype=np.int32)
+    o = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64)
+    n = batch if batch is not None else (0 if s is None else len(s))
+    st = lib.chw_plan(ctypes.byref(h), n,
+                      None if s is None else s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                      None if o is None else o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      dtype, norm, flags)
+    return st, h
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(sizes=[10], batch=-1), 1),
+    (dict(sizes=None, batch=3), 1),
+    (dict(sizes=[10], dtype=9), 1),
+    (dict(sizes=[10], norm=5), 1),
+    (dict(sizes=[10], dtype=3, norm=0), 2),            # int32 orthonormal
+    (dict(sizes=[10], flags=1 << 9), 1),               # unknown flag
+    (dict(sizes=[10], flags=(1 << 2) | (1 << 3)), 1),  # exclusive flags
+    (dict(sizes=[-1]), 1),
+    (dict(sizes=[31]), 1),
+    (dict(sizes=[28]), 2),                             # beyond this build
+    (dict(sizes=[21], dtype=4), 2),                    # F64 limit
+    (dict(sizes=[4, 4], offsets=[0, 8, 24]), 1),       # overlap
+    (dict(sizes=[4, 4], offsets=[0, 16, 20]), 1),      # end below last signal
+    (dict(sizes=[4], offsets=[-4, 12]), 1),            # negative
+    (dict(sizes=[4, 4], offsets=[0, 17, 40]), 3),      # misaligned
+    (dict(sizes=[1, 4], offsets=[1, 4, 40]), 0),       # tiny signal may be unaligned
+])
+def test_plan_validation(case, expect):
+    st, h = _plan_raw(**case)
+    assert st == expect, (case, chw.load().chw_last_error())
+    if st == 0:
+        assert chw.load().chw_plan_destroy(h) == 0
+    else:
+        assert not h.value
+        assert chw.load().chw_last_error().decode()
+
+
+def test_null_plan_arguments():
+    lib = chw.load()
+    n = ctypes.c_size_t()
+    assert lib.chw_workspace_size(None, ctypes.byref(n)) == 1
+    assert lib.chw_forward(None, None, None, None, None) == 1
+    assert lib.chw_backward(None, None, None, None, None) == 1
+    assert lib.chw_plan_destroy(None) == 0
+    assert lib.chw_plan_set_option(None, b"lr12", 5) == 1
+
+
+def test_empty_batch_is_a_noop():
+    st, h = _plan_raw([])
+    assert st == 0
+    lib = chw.load()
+    assert lib.chw_forward(h, None, None, None, None) == 0
+    assert lib.chw_plan_destroy(h) == 0
+
+
+def test_no_device_path():
+    # This container has no GPU: compute calls must say so, not crash.
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    p = chw.Plan([10, 10])
+    lib = chw.load()
+    buf = (ctypes.c_char * 64)()
+    st = lib.chw_forward(p.handle, ctypes.addressof(buf), ctypes.addressof(buf), None, None)
+    # host buffer is 16-byte aligned by ctypes or not; either misaligned or no device
+    assert st in (3, 5)
+    aligned = ctypes.create_string_buffer(8192 * 4 + 64)
+    a = (ctypes.addressof(aligned) + 15) & ~15
+    st = lib.chw_forward(p.handle, ctypes.c_void_p(a), ctypes.c_void_p(a), None, None)
+    assert st == 5, lib.chw_last_error()
+
+
+def test_describe_and_planner_properties():
+    # uniform large signals: two passes, the split covers every level once
+    p = chw.Plan([20] * 3, dtype="f32")
+    d = p.describe()
+    plan = d["plan"]
+    assert plan["multi"] == 3 and plan["single"] == 0
+    sp = plan["splits"][0]
+    assert sp["m"] == 20 and sp["L1"] + (20 - sp["L1"]) == 20
+    assert sp["L1"] <= sp["K1"] and 20 - sp["L1"] <= sp["K2"]
+    assert p.workspace_size() == 3 * (1 << 20) * 4
+    fw = plan["forward"]
+    assert {r["phase"] for r in fw} == {0, 1}
+    # first-pass items: 2^(m - L1) rows in tiles of 2^rows_log2 rows; last-pass
+    # items: 2^L1 blocks of 2^(m - L1)
+    rows_tiles = (1 << (20 - sp["L1"])) >> sp["rows_log2"]
+    last_tiles = (1 << 20) >> sp["K2"]
+    assert plan["items"] == 3 * (rows_tiles + last_tiles)
+    p.close()
+
+
+def test_planner_ragged_and_options():
+    # tiny signals last so that packing keeps every larger signal aligned
+    sizes = [3, 6, 6, 6, 12, 13, 15, 16, 20, 24, 27, 2, 1, 0]
+    p = chw.Plan(sizes, dtype="bf16")
+    d = p.describe()["plan"]
+    assert d["tiny"] == 3          # 2^m * 2 bytes < 16: m = 0, 1, 2
+    assert d["single"] == 7        # 3, 6, 6, 6, 12, 13, 15
+    assert d["multi"] == 4
+    ms = sorted(s["m"] for s in d["splits"])
+    assert ms == [16, 20, 24, 27]
+    for s in d["splits"]:
+        assert s["m"] - s["L1"] <= s["K2"] and s["m"] - s["L1"] >= s["rows_log2"]
+    # forced split and register options rebuild the plan
+    p2 = chw.Plan([20, 20], dtype="f32")
+    p2.set_option("split_l1", 10)
+    assert p2.describe()["plan"]["splits"][0]["L1"] == 10
+    p2.set_option("lr12", 5)
+    assert p2.describe()["plan"]["config"]["lr12"] == 5
+    with pytest.raises(chw.CHWError):
+        p2.set_option("lr12", 7)
+    with pytest.raises(chw.CHWError):
+        p2.set_option("nonsense", 1)
+    p3 = chw.Plan([14, 14], dtype="f32")
+    p3.set_option("single15", 0)
+    assert p3.describe()["plan"]["multi"] == 2
+
+
+def test_packed_misaligned_signal_is_rejected():
+    # packed back to back, 1 + 2 + 4 elements put the 8-element bf16 signal at
+    # element 7: not 16-byte aligned
+    with pytest.raises(chw.CHWError) as e:
+        chw.Plan([0, 1, 2, 3], dtype="bf16")
+    assert e.value.name == "CHW_ERR_MISALIGNED"
+
+
+def test_planner_packs_small_signals():
+    p = chw.Plan([10] * 64, dtype="f32")
+    d = p.describe()["plan"]
+    assert d["items"] == 16 and d["list"] == 0      # 4 consecutive signals per tile
+    # gaps force an offset list
+    offs = np.arange(65, dtype=np.int64) * 2048
+    p = chw.Plan([10] * 64, dtype="f32", offsets=offs)
+    d = p.describe()["plan"]
+    assert d["items"] == 16 and d["list"] == 64
+
+
+def test_layout_selfcheck():
+    ok, rep = chw.layout_selfcheck()
+    assert ok, [r for r in rep if not r.get("ok", True)]
+    phases = {r["phase"] for r in rep if "phase" in r}
+    assert phases == {"rounds", "contig", "paley", "transposed"}

@@ -1,0 +1,270 @@
+"""Parity of the HIP path with the oracle (GPU).  Every comparison is element
+by element against the plain CPU oracle on the same seeded inputs."""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cascade, metrics
+from paper_1609_06641_amd import chw
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    t = gu.torch()
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    chw.load()
+
+
+def _sync():
+    gu.torch().cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# the small plain workload: 64 x 2^10, float32 orthonormal and int32 exact
+
+def test_plain_small_f32():
+    w = workloads.CONFIGS["plain_small_f32"]
+    x = workloads.float_signals(w.seed, w.batch, 10)
+    p = chw.Plan([10] * w.batch, dtype="f32")
+    y = p.forward(gu.dev_tensor(x, "f32"))
+    _sync()
+    ref = cascade.chw_forward(x.astype(np.float64))
+    rel = metrics.rel_l2(gu.host_f64(y).reshape(w.batch, -1), ref)
+    print("max rel-L2", rel.max())
+    assert rel.max() <= 1e-5
+
+
+def test_plain_small_i32_bit_exact():
+    w = workloads.CONFIGS["plain_small_i32"]
+    x = workloads.int_signals(w.seed, w.batch, 10)
+    p = chw.Plan([10] * w.batch, dtype="i32", norm="none")
+    y = p.forward(gu.dev_tensor(x, "i32"))
+    _sync()
+    ref = cascade.chw_forward(x.astype(np.int64))
+    assert np.abs(ref).max() < 2 ** 31
+    assert np.array_equal(gu.host_i64(y).reshape(w.batch, -1), ref)
+
+
+# ---------------------------------------------------------------------------
+# every size 0..22: single pass, two passes, in place and out of place
+
+def _batch_for(m):
+    return 3 if m <= 16 else (2 if m <= 20 else 1)
+
+
+@pytest.mark.parametrize("m", list(range(0, 23)))
+def test_sizes_f32_i32(m):
+    b = _batch_for(m)
+    xf = workloads.float_signals(100 + m, b, m)
+    xi = workloads.int_signals(200 + m, b, m)
+    sizes = [m] * b
+    pf = chw.Plan(sizes, dtype="f32")
+    pi = chw.Plan(sizes, dtype="i32", norm="none")
+    ref_f = gu.oracle_packed(xf.reshape(-1).astype(np.float64), sizes)
+    ref_i = gu.oracle_packed(xi.reshape(-1).astype(np.int64), sizes)
+    # out of place (no workspace)
+    yf = pf.forward(gu.dev_tensor(xf.reshape(-1), "f32"))
+    yi = pi.forward(gu.dev_tensor(xi.reshape(-1), "i32"))
+    # in place (workspace when two passes)
+    tf = gu.dev_tensor(xf.reshape(-1), "f32")
+    pf.forward(tf, out=tf)
+    ti = gu.dev_tensor(xi.reshape(-1), "i32")
+    pi.forward(ti, out=ti)
+    _sync()
+    for got in (yf, tf):
+        rel = gu.per_signal_rel(gu.host_f64(got), ref_f, sizes)
+        assert rel.max() <= 1e-5, (m, rel.max())
+    assert np.abs(ref_i).max() < 2 ** 31
+    for got in (yi, ti):
+        assert np.array_equal(gu.host_i64(got), ref_i), m
+
+
+@pytest.mark.parametrize("m", [3, 10, 12, 14, 16, 20])
+def test_backward_equals_forward_and_oracle(m):
+    # H is symmetric: the reversed cascade of transposed factors gives the
+    # same numbers; with the same butterfly operands and the scale applied
+    # last, bitwise the same.
+    b = _batch_for(m)
+    x = workloads.float_signals(300 + m, b, m).reshape(-1)
+    sizes = [m] * b
+    p = chw.Plan(sizes, dtype="f32")
+    xd = gu.dev_tensor(x, "f32")
+    yf = p.forward(xd)
+    yb = p.backward(xd)
+    _sync()
+    assert np.array_equal(gu.host_f64(yf), gu.host_f64(yb))
+    ref = gu.oracle_packed(x.astype(np.float64), sizes, adjoint=True)
+    assert gu.per_signal_rel(gu.host_f64(yb), ref, sizes).max() <= 1e-5
+    xi = workloads.int_signals(400 + m, b, m).reshape(-1)
+    pi = chw.Plan(sizes, dtype="i32", norm="none")
+    ybi = pi.backward(gu.dev_tensor(xi, "i32"))
+    _sync()
+    assert np.array_equal(gu.host_i64(ybi), gu.oracle_packed(xi.astype(np.int64), sizes,
+                                                              adjoint=True))
+
+
+# ---------------------------------------------------------------------------
+# precision forms: bf16 / f16 storage, FP32 inside every pass
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("m,batch", [(12, 8192), (6, 64), (14, 16), (17, 4), (20, 2)])
+def test_precision_forms(dtype, m, batch):
+    x32 = workloads.outlier_signals(3001 if m == 12 else 3100 + m, batch, m)
+    xh = workloads.to_half_precision(x32, dtype)          # RNE-rounded inputs
+    x64 = xh.to(gu.torch().float64).numpy().reshape(-1)  # exact
+    sizes = [m] * batch
+    p = chw.Plan(sizes, dtype=dtype)
+    y = p.forward(gu.dev_tensor(xh.reshape(-1), dtype))
+    yb = p.backward(gu.dev_tensor(xh.reshape(-1), dtype))
+    _sync()
+    ref = gu.oracle_packed(x64, sizes, threads=16)
+    rel = gu.per_signal_rel(gu.host_f64(y), ref, sizes)
+    print("%s m=%d max rel-L2 %.3e pooled %.3e" % (dtype, m, rel.max(),
+          metrics.pooled_rel_l2(gu.host_f64(y), ref)))
+    assert rel.max() <= 4e-3
+    assert np.array_equal(gu.host_f64(y), gu.host_f64(yb))
+
+
+# ---------------------------------------------------------------------------
+# ragged batches with gaps: sentinels in the gaps stay untouched
+
+@pytest.mark.parametrize("dtype", ["f32", "i32", "bf16", "f16", "f64"])
+def test_ragged_with_gaps(dtype):
+    rng = np.random.default_rng(77)
+    ms = rng.integers(0, 19 if dtype != "f64" else 17, size=40).astype(np.int32)
+    ms[:6] = [0, 1, 2, 3, 12, 16]
+    es = {"f32": 4, "i32": 4, "bf16": 2, "f16": 2, "f64": 8}[dtype]
+    align = 16 // es
+    offs = []
+    o = 0
+    for k in ms:
+        o += int(rng.integers(0, 3)) * align          # gap before the signal
+        offs.append(o)
+        o += max(1 << int(k), align)
+    offs.append(o + align)
+    offs = np.array(offs, dtype=np.int64)
+    total = int(offs[-1])
+    norm = "none" if dtype == "i32" else "ortho"
+    if dtype == "i32":
+        x = rng.integers(-128, 128, size=total).astype(np.int32)
+        sentinel = 123456789
+    else:
+        x = rng.standard_normal(total).astype(np.float32)
+        sentinel = 4242.0
+    p = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs)
+    xd = gu.dev_tensor(x, dtype)
+    y = gu.dev_tensor(np.full(total, sentinel, dtype=x.dtype), dtype)
+    p.forward(xd, out=y)
+    _sync()
+    mask = np.ones(total, dtype=bool)
+    for k, o in zip(ms, offs[:-1]):
+        mask[o:o + (1 << int(k))] = False
+    if dtype == "i32":
+        got = gu.host_i64(y)
+        ref = gu.oracle_packed(x.astype(np.int64), ms, offs)
+        assert np.array_equal(got[~mask], ref[~mask])
+        assert np.all(got[mask] == sentinel)
+    else:
+        xin = gu.host_f64(xd)
+        got = gu.host_f64(y)
+        ref = gu.oracle_packed(xin, ms, offs)
+        rel = gu.per_signal_rel(got, ref, ms, offs)
+        assert rel.max() <= gu.TOL[dtype], rel.max()
+        assert np.all(got[mask] == float(gu.torch().tensor(sentinel).to(
+            getattr(gu.torch(), gu.TORCH_DT[dtype])).double()))
+
+
+# ---------------------------------------------------------------------------
+# numerics do not depend on tiling or pass split; graph replay
+
+def test_split_invariance_bitwise():
+    sizes = [14] * 3 + [20] * 2 + [9] * 5
+    x = np.concatenate([workloads.float_signals(500 + i, 1, k).reshape(-1)
+                        for i, k in enumerate(sizes)])
+    xd = gu.dev_tensor(x, "f32")
+    outs = []
+    configs = [dict(), dict(lr12=5), dict(lr15=6), dict(single15=0),
+               dict(split_l1=9), dict(split_l1=10), dict(split_l1=12, lr15=6)]
+    for cfg in configs:
+        p = chw.Plan(sizes, dtype="f32")
+        for k, v in cfg.items():
+            p.set_option(k, v)
+        outs.append(gu.host_f64(p.forward(xd)))
+    _sync()
+    for cfg, o in zip(configs[1:], outs[1:]):
+        assert np.array_equal(o, outs[0]), cfg
+    ref = gu.oracle_packed(x.astype(np.float64), sizes)
+    assert gu.per_signal_rel(outs[0], ref, sizes).max() <= 1e-5
+
+
+def test_graph_replay():
+    sizes = [16] * 2 + [7] * 9
+    x = np.concatenate([workloads.float_signals(600 + i, 1, k).reshape(-1)
+                        for i, k in enumerate(sizes)])
+    t = gu.torch()
+    p = chw.Plan(sizes, dtype="f32", graph=True)
+    plain = chw.Plan(sizes, dtype="f32")
+    xd = gu.dev_tensor(x, "f32")
+    ref = gu.host_f64(plain.forward(xd))
+    y = t.empty_like(xd)
+    for r in range(5):
+        y.fill_(float(r))
+        p.forward(xd, out=y)
+        _sync()
+        assert np.array_equal(gu.host_f64(y), ref), r
+    # new buffers: the graph is re-captured for them
+    x2 = xd * 2
+    y2 = t.empty_like(xd)
+    p.forward(x2, out=y2)
+    _sync()
+    assert np.array_equal(gu.host_f64(y2), gu.host_f64(plain.forward(x2)))
+    gb = p.backward(xd)
+    _sync()
+    assert np.array_equal(gu.host_f64(gb), ref)
+
+
+def test_f64_verify_kernel():
+    sizes = [6] * 4 + [12] * 2 + [16, 20]
+    x = np.concatenate([np.random.default_rng(700 + i).standard_normal(1 << k)
+                        for i, k in enumerate(sizes)])
+    p = chw.Plan(sizes, dtype="f64")
+    y = p.forward(gu.dev_tensor(x, "f64"))
+    yb = p.backward(gu.dev_tensor(x, "f64"))
+    _sync()
+    ref = gu.oracle_packed(x, sizes)
+    assert gu.per_signal_rel(gu.host_f64(y), ref, sizes).max() <= 1e-13
+    assert np.array_equal(gu.host_f64(y), gu.host_f64(yb))
+
+
+def test_unnormalized_float():
+    sizes = [11] * 4
+    x = workloads.int_signals(800, 4, 11).reshape(-1)
+    p = chw.Plan(sizes, dtype="f32", norm="none")
+    y = p.forward(gu.dev_tensor(x.astype(np.float32), "f32"))
+    _sync()
+    ref = gu.oracle_packed(x.astype(np.int64), sizes)
+    assert np.array_equal(gu.host_f64(y), ref.astype(np.float64))  # exact: |y| < 2^24
+
+
+def test_streams_concurrent():
+    t = gu.torch()
+    sizes = [18] * 2
+    x = workloads.float_signals(900, 2, 18).reshape(-1)
+    ref = gu.oracle_packed(x.astype(np.float64), sizes)
+    p = chw.Plan(sizes, dtype="f32")
+    s1, s2 = t.cuda.Stream(), t.cuda.Stream()
+    xd = gu.dev_tensor(x, "f32")
+    t.cuda.synchronize()
+    outs = []
+    for s in (s1, s2):
+        with t.cuda.stream(s):
+            ws = t.empty(p.workspace_size(), dtype=t.uint8, device="cuda")
+            outs.append(p.forward(xd, workspace=ws, stream=s))
+    t.cuda.synchronize()
+    for o in outs:
+        assert gu.per_signal_rel(gu.host_f64(o), ref, sizes).max() <= 1e-5
