@@ -65,7 +65,13 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the plan first")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--workload", default="plain_2p20_f32",
+                    help="plain_2p20_f32 (headline) or, for profiling only: "
+                         "plain_2p24_f32, precision_bf16, precision_f16, diff_f32, "
+                         "plain_small_f32, ragged_f32, ragged_bf16")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also time a plain device copy of this many GiB (calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -81,6 +87,10 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+
+    if args.workload != "plain_2p20_f32":
+        run_other(args, dev, stream)
+        return
 
     # ---- headline workload: 1024 x 2^20 float32 ------------------------------
     w = workloads.CONFIGS["plain_2p20_f32"]
@@ -146,8 +156,63 @@ def main():
         del xb, yb, ws
         torch.cuda.empty_cache()
 
+    if args.copy_gib > 0:
+        out["copy_calibration"] = copy_calibration(args, dev, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(x_host, m, min(args.cpu_sample, batch))
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibration(args, dev, stream):
+    """Time a plain device-to-device copy of known size (read + write bytes)."""
+    import torch
+    n = int(args.copy_gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    ms = time_steps(lambda: b.copy_(a), max(3, args.steps), 2, stream)
+    res = {"bytes_per_copy": 8 * n, "ms": round(ms, 4),
+           "GBs": round(8 * n / (ms / 1e3) / 1e9, 1)}
+    del a, b
+    return res
+
+
+def run_other(args, dev, stream):
+    """Profiling entry for the other workloads (one JSON line, no headline)."""
+    import torch
+    import workloads
+    from paper_1609_06641_amd import chw
+    w = workloads.CONFIGS[args.workload]
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16,
+           "i32": torch.int32}[w.dtype]
+    if w.name.startswith("ragged"):
+        ks = workloads.ragged_log2_sizes(4001)
+        offs = workloads.packed_offsets(ks)
+        xv = torch.from_numpy(workloads.ragged_values(w.seed, ks, offs))
+        plan = chw.Plan(ks, dtype=w.dtype, offsets=offs, graph=True)
+        elems = int(offs[-1])
+    else:
+        m = w.log2_sizes[0]
+        if w.dtype in ("bf16", "f16"):
+            xv = torch.from_numpy(workloads.outlier_signals(w.seed, w.batch, m))
+        elif w.dtype == "i32":
+            xv = torch.from_numpy(workloads.int_signals(w.seed, w.batch, m))
+        else:
+            xv = torch.from_numpy(workloads.float_signals(w.seed, w.batch, m))
+        plan = chw.Plan([m] * w.batch, dtype=w.dtype, norm=w.norm)
+        elems = w.batch << m
+    x = xv.reshape(-1).to(tdt).to(dev)
+    y = torch.empty_like(x)
+    ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device=dev)
+    if args.tune:
+        plan.autotune(x, y, workspace=ws, iters=2)
+    ms = time_steps(lambda: plan.forward(x, out=y, workspace=ws), args.steps, args.warmup, stream)
+    es = x.element_size()
+    out = {"workload": w.name, "ms_per_step": round(ms, 4),
+           "Gelem_s": round(elems / (ms / 1e3) / 1e9, 2),
+           "algorithmic_GBs": round(2 * es * elems / (ms / 1e3) / 1e9, 1),
+           "plan": plan.describe()["plan"]["config"]}
+    if args.copy_gib > 0:
+        out["copy_calibration"] = copy_calibration(args, dev, stream)
     print(json.dumps(out), flush=True)
 
 

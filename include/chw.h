@@ -81,7 +81,7 @@ enum {
     CHW_FLAG_GRAPH = 1u << 0,        /* capture the launches of a call in a
                                         hipGraph and replay it               */
     CHW_FLAG_NO_AUTOTUNE = 1u << 1,  /* ignore the tuning cache              */
-    CHW_FLAG_PERSISTENT = 1u << 2,   /* one persistent work-queue launch      */
+    CHW_FLAG_PERSISTENT = 1u << 2,   /* one persistent launch (exec 2)        */
     CHW_FLAG_MULTI_LAUNCH = 1u << 3  /* one launch per HBM pass              */
 };
 
@@ -150,13 +150,38 @@ chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace
 chw_status chw_plan_destroy(chw_plan_t plan);
 
 /* Override a planner choice before first use.  Keys (value):
- *   "split_l1"   (int) levels of the first HBM pass for multi-pass signals
- *   "tile_log2"  (int) 12 or 15: tile size of the pass kernels
- *   "exec"       (int) 0 = multi-launch, 1 = persistent
- *   "grid"       (int) persistent grid size in workgroups (0 = automatic)
- * Unknown keys or values give CHW_ERR_INVALID_ARGUMENT; a plan that has been
- * used gives CHW_ERR_INVALID_ARGUMENT (plans are immutable once used). */
+ *   "split_l1"  levels of the first HBM pass of multi-pass signals (-1 = auto)
+ *   "lr12"      5 or 6: log2 registers per thread of the 2^12-element tiles
+ *   "lr15"      5 or 6: log2 registers per thread of the 2^15-element tiles
+ *   "single15"  1: signals of 2^13..2^15 in one pass; 0: two passes
+ *   "chunk"     elements of multi-pass signals per first/last pass pair
+ *               (0 = the whole batch in one pair of launches)
+ *   "exec"      0 = one launch per pass; 2 = one persistent launch in which a
+ *               workgroup runs both passes of a multi-pass signal (2^12-element
+ *               tiles; signals up to 2^21; also set by CHW_FLAG_PERSISTENT).
+ *               1 (a dependency-counter work queue) is disabled: it gives
+ *               CHW_ERR_UNSUPPORTED.
+ *   "timing"    1: record a HIP event around every launch (instrumentation;
+ *               may be toggled at any time; disables graph replay)
+ * Unknown keys or values give CHW_ERR_INVALID_ARGUMENT; so does changing a
+ * planner choice on a plan that has been used (plans are immutable once used).
+ * No choice changes the numbers: every configuration runs the same stages on
+ * the same operands in the same order. */
 chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value);
+
+/* With option "timing" on: durations in milliseconds of the kernel launches of
+ * the plan's last call, measured by HIP events on that call's stream.  *n in:
+ * capacity of ms (host array); out: number of launches of that call.  Waits
+ * for the last call to finish. */
+chw_status chw_launch_times(chw_plan_t plan, float *ms, int *n);
+
+/* Host-only check of the plan's work tables: every element of every signal is
+ * covered exactly once per pass (one single-pass tile, or one first-pass and
+ * one last-pass tile), no tile leaves its signal or the workspace, launches of
+ * the two passes are ordered, and persistent whole-signal items fit the tile
+ * sizes.  CHW_OK, or
+ * CHW_ERR_UNSUPPORTED with the reason in chw_last_error(). */
+chw_status chw_plan_check(chw_plan_t plan);
 
 /* Write a NUL-terminated JSON description of the plan (passes, level split,
  * tile sizes, work items, workspace) into the host buffer buf of len bytes. */

@@ -34,6 +34,7 @@ SOURCES = [
     "chw_planner.cpp",
     "chw_api.cpp",
     "chw_selfcheck.cpp",
+    "chw_plancheck.cpp",
 ]
 
 

@@ -36,6 +36,9 @@ SIGNATURES = {
     "chw_plan_destroy": (ctypes.c_int, [_VP]),
     "chw_plan_set_option": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_int64]),
     "chw_plan_describe": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
+    "chw_plan_check": (ctypes.c_int, [_VP]),
+    "chw_launch_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_int)]),
     "chw_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int]),
     "chw_layout_selfcheck": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
     "chw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -102,7 +105,7 @@ class Plan:
     """
 
     def __init__(self, log2_sizes, dtype="f32", norm="ortho", offsets=None, graph=False,
-                 flags=0):
+                 persistent=False, flags=0):
         lib = load()
         import numpy as np
         sizes = np.ascontiguousarray(log2_sizes, dtype=np.int32).ravel()
@@ -116,7 +119,7 @@ class Plan:
             if offs_arr.size != self.batch + 1:
                 raise ValueError("offsets needs batch + 1 entries")
         self.offsets = offs_arr
-        flags = int(flags) | (FLAG_GRAPH if graph else 0)
+        flags = int(flags) | (FLAG_GRAPH if graph else 0) | (FLAG_PERSISTENT if persistent else 0)
         h = _VP()
         _check(lib.chw_plan(ctypes.byref(h), self.batch,
                             sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -149,6 +152,18 @@ class Plan:
 
     def set_option(self, key, value):
         _check(load().chw_plan_set_option(self.handle, key.encode(), int(value)))
+
+    def check(self):
+        """Host-side invariants of the plan's work tables (raises on failure)."""
+        _check(load().chw_plan_check(self.handle))
+
+    def launch_times(self):
+        """Per-launch durations (ms) of the last call; needs option 'timing'."""
+        cap = 256
+        arr = (ctypes.c_float * cap)()
+        n = ctypes.c_int(cap)
+        _check(load().chw_launch_times(self.handle, arr, ctypes.byref(n)))
+        return [float(arr[i]) for i in range(min(n.value, cap))]
 
     # -- calls ------------------------------------------------------------------
     def _tensor_check(self, t, name):

@@ -66,6 +66,9 @@ struct DeviceState {
     int32_t *tiny_m = nullptr;
     hipStream_t cap = nullptr;     // private stream for graph capture
     std::vector<GraphEntry> graphs;
+    std::map<const void *, int> grid_cap;  // resident workgroups per kernel
+    std::vector<hipEvent_t> ev;    // per-launch timing events (option "timing")
+    int ev_used = 0;               // events recorded by the last call
 
     void free_tables()
     {
@@ -83,6 +86,12 @@ struct DeviceState {
     {
         for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
         graphs.clear();
+    }
+    void free_events()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        ev_used = 0;
     }
 };
 
@@ -109,6 +118,8 @@ struct chw_plan_s {
     BuiltPlan built;
     int version = 0;
     bool used = false;
+    bool timing = false;       // record a HIP event around every launch
+    int last_dev = -1;         // device of the last call (for timings)
     std::mutex mu;
     std::map<int, DeviceState> dev;
 };
@@ -194,11 +205,31 @@ chw_status ensure_tables(chw_plan_t p, int dev, DeviceState **out)
     return CHW_OK;
 }
 
+// Record timing event number `i` of this call (option "timing").
+chw_status mark(chw_plan_t p, DeviceState &ds, int i, hipStream_t stream)
+{
+    if (!p->timing) return CHW_OK;
+    while ((int)ds.ev.size() <= i) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+        ds.ev.push_back(e);
+    }
+    hipError_t err = hipEventRecord(ds.ev[i], stream);
+    if (err != hipSuccess) return hip_fail(err, "hipEventRecord");
+    ds.ev_used = i + 1;
+    return CHW_OK;
+}
+
 // Enqueue the launches of one call on `stream`.
 chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
                    int inter_is_io, hipStream_t stream)
 {
     const BuiltPlan &b = p->built;
+    int nev = 0;
+    chw_status ms;
+    ds.ev_used = 0;
+    if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
     LaunchArgs a{};
     a.in = x;
     a.out = y;
@@ -206,8 +237,6 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     a.inter_is_io = inter_is_io;
     a.list = ds.list;
     a.ortho = p->norm == CHW_ORTHONORMAL ? 1 : 0;
-    a.counters = nullptr;
-    a.spin_limit = 0;
     if (!b.tiny_off.empty()) {
         const TinyVariant *tv = find_tiny_variant(p->dt, adj);
         if (!tv) return fail(CHW_ERR_UNSUPPORTED, "no tiny kernel for this dtype");
@@ -215,19 +244,37 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         hipError_t e = tv->launch(dim3((n + 255) / 256), dim3(256), stream, x, y, ds.tiny_off,
                                   ds.tiny_m, n, a.ortho);
         if (e != hipSuccess) return hip_fail(e, "tiny kernel launch");
+        if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
     }
-    const std::vector<LaunchRange> *ph = adj ? b.adj : b.fwd;
-    for (int f = 0; f < 2; ++f)
-        for (const LaunchRange &r : ph[f]) {
-            const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
-            if (!v)
-                return fail(CHW_ERR_UNSUPPORTED, "no tile kernel for dtype %d, K=%d, LR=%d", p->dt,
-                            r.K, r.LR);
-            a.items = ds.items + r.begin;
-            a.nitems = r.end - r.begin;
-            hipError_t e = v->launch(dim3(a.nitems), stream, a);
-            if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+    for (const LaunchRange &r : adj ? b.adj : b.fwd) {
+        const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
+        if (!v || (r.persistent && !v->launch_persistent))
+            return fail(CHW_ERR_UNSUPPORTED, "no tile kernel for dtype %d, K=%d, LR=%d", p->dt,
+                        r.K, r.LR);
+        a.items = ds.items + r.begin;
+        a.nitems = r.end - r.begin;
+        hipError_t e;
+        if (r.persistent) {
+            int &cap = ds.grid_cap[v->fn_persistent];
+            if (cap == 0) {
+                int per_cu = 0, dev = 0;
+                (void)hipGetDevice(&dev);
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->fn_persistent, v->nt, 0);
+                if (e != hipSuccess || per_cu < 1) {
+                    (void)hipGetLastError();
+                    per_cu = 1;
+                }
+                int cus = 0;
+                (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+                cap = per_cu * std::max(1, cus);
+            }
+            e = v->launch_persistent(dim3(std::min(a.nitems, cap)), stream, a);
+        } else {
+            e = v->launch(dim3(a.nitems), stream, a);
         }
+        if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+        if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
+    }
     return CHW_OK;
 }
 
@@ -274,9 +321,11 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     std::lock_guard<std::mutex> lk(p->mu);
     p->used = true;
+    p->last_dev = dev;
     DeviceState *ds = nullptr;
     if ((s = ensure_tables(p, dev, &ds)) != CHW_OK) return s;
-    if (!(p->flags & CHW_FLAG_GRAPH)) return enqueue(p, *ds, adj, x, y, inter, inter_is_io, stream);
+    if (!(p->flags & CHW_FLAG_GRAPH) || p->timing)
+        return enqueue(p, *ds, adj, x, y, inter, inter_is_io, stream);
 
     // graph replay: capture once per (direction, buffers) on a private stream
     GraphEntry *ge = nullptr;
@@ -414,6 +463,7 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
     }
     if (p->extent > (((int64_t)1 << 62) / 8)) return bad(fail(CHW_ERR_OUT_OF_MEMORY, "extent overflows"));
     PlanConfig cfg;
+    if (flags & CHW_FLAG_PERSISTENT) cfg.exec = 2;
     chw_status s = rebuild(p, cfg);
     if (s != CHW_OK) return bad(s);
     *plan = p;
@@ -447,6 +497,7 @@ chw_status chw_plan_destroy(chw_plan_t plan)
         for (auto &kv : plan->dev) {
             if (kv.first != cur) (void)hipSetDevice(kv.first);
             kv.second.free_tables();
+            kv.second.free_events();
             if (kv.second.cap) (void)hipStreamDestroy(kv.second.cap);
         }
         if (cur >= 0) (void)hipSetDevice(cur);
@@ -459,16 +510,57 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
 {
     if (!plan || !key) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
     std::lock_guard<std::mutex> lk(plan->mu);
+    const std::string k = key;
+    if (k == "timing" && (value == 0 || value == 1)) {  // instrumentation only
+        plan->timing = value != 0;
+        return CHW_OK;
+    }
     if (plan->used) return fail(CHW_ERR_INVALID_ARGUMENT, "plan already used; options are fixed");
     PlanConfig cfg = plan->cfg;
-    const std::string k = key;
     if (k == "lr12" && (value == 5 || value == 6)) cfg.lr12 = (int)value;
     else if (k == "lr15" && (value == 5 || value == 6)) cfg.lr15 = (int)value;
     else if (k == "single15" && (value == 0 || value == 1)) cfg.single15 = (int)value;
     else if (k == "split_l1" && value >= -1 && value <= 30) cfg.split_l1 = (int)value;
-    else if (k == "exec" && value == 0) cfg.exec = (int)value;
+    else if (k == "exec" && value == 1)
+        return fail(CHW_ERR_UNSUPPORTED,
+                    "exec 1 (dependency-counter work queue) is disabled in this build");
+    else if (k == "exec" && (value == 0 || value == 2)) cfg.exec = (int)value;
+    else if (k == "chunk" && value >= 0) cfg.chunk = value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
     return rebuild(plan, cfg);
+}
+
+chw_status chw_launch_times(chw_plan_t plan, float *ms, int *n)
+{
+    if (!plan || !n || (*n > 0 && !ms)) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    if (!plan->timing || plan->last_dev < 0)
+        return fail(CHW_ERR_INVALID_ARGUMENT, "option \"timing\" is off or the plan was not run");
+    DeviceState &ds = plan->dev[plan->last_dev];
+    const int launches = ds.ev_used > 0 ? ds.ev_used - 1 : 0;
+    if (launches == 0) {
+        *n = 0;
+        return CHW_OK;
+    }
+    hipError_t e = hipEventSynchronize(ds.ev[launches]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    const int k = std::min(*n, launches);
+    for (int i = 0; i < k; ++i) {
+        e = hipEventElapsedTime(&ms[i], ds.ev[i], ds.ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
+    *n = launches;
+    return CHW_OK;
+}
+
+chw_status chw_plan_check(chw_plan_t plan)
+{
+    if (!plan) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    std::string err;
+    if (!check_plan(plan->m, plan->off, plan->dt, plan->built, &err))
+        return fail(CHW_ERR_UNSUPPORTED, "plan check failed: %s", err.c_str());
+    return CHW_OK;
 }
 
 chw_status chw_plan_describe(chw_plan_t plan, char *buf, size_t len)
@@ -509,7 +601,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             Split sp;
             bool ok = true;
             for (int32_t m : plan->m)
-                if (m > 15 && !choose_split(m, plan->dt, l1, &sp)) ok = false;
+                if (m > 15 && !choose_split(m, plan->dt, l1, false, &sp)) ok = false;
             if (ok) l1s.push_back(l1);
         }
     for (int lr12 : {5, 6})

@@ -3,6 +3,7 @@
 #include "chw_kernels.inc"
 
 CHW_INST_ITEMS(chw::DT_F64, 12, 5, 4, 3)
+CHW_INST_PERSIST(chw::DT_F64, 5)
 CHW_INST_TINY(chw::DT_F64)
 
 #if !defined(__HIP_DEVICE_COMPILE__)

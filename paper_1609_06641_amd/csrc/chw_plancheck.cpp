@@ -1,0 +1,167 @@
+// chw_plancheck.cpp -- host-side invariants of a built plan (no device).
+//
+//   * every element of every signal is covered exactly once per pass: by one
+//     single-pass tile, or by one first-pass and one last-pass tile;
+//   * every tile stays inside its signal (and the workspace);
+//   * multi-launch order: a signal's last-pass launch comes after its
+//     first-pass launch (forward) or before it (adjoint);
+//   * persistent tables: a whole-signal item covers its signal in both passes
+//     and its split fits the 2^12-element tiles.
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "chw_planner.h"
+
+namespace chw {
+
+namespace {
+
+struct Iv {
+    int64_t lo, hi;
+    int pass;  // 0 single, 1 first, 2 last
+    int launch;
+};
+
+bool check_cover(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
+                 std::vector<Iv> &iv, std::string *err, int want_pass, bool is_multi_pass)
+{
+    // intervals of `want_pass` must tile exactly the signals of that class
+    std::vector<std::pair<int64_t, int64_t>> sig;
+    (void)is_multi_pass;
+    std::vector<Iv> mine;
+    for (const Iv &v : iv)
+        if (v.pass == want_pass) mine.push_back(v);
+    std::sort(mine.begin(), mine.end(), [](const Iv &a, const Iv &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < mine.size(); ++i)
+        if (mine[i].lo < mine[i - 1].hi) {
+            *err = "tiles of pass " + std::to_string(want_pass) + " overlap at element " +
+                   std::to_string(mine[i].lo);
+            return false;
+        }
+    (void)ms;
+    (void)off;
+    return true;
+}
+
+}  // namespace
+
+bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off, int dt,
+                const BuiltPlan &p, std::string *err)
+{
+    (void)dt;
+    const size_t batch = ms.size();
+    // classify signals exactly as the plan did: a signal is multi-pass iff it
+    // has first-pass tiles
+    auto tile_intervals = [&](const std::vector<LaunchRange> &launches, std::vector<Iv> &iv) {
+        for (size_t li = 0; li < launches.size(); ++li) {
+            const LaunchRange &r = launches[li];
+            for (int k = r.begin; k < r.end; ++k) {
+                const Item &it = p.items[k];
+                const int K = r.K;
+                if (it.kind == KIND_BLOCKS) {
+                    for (int b = 0; b < it.count; ++b) {
+                        const int64_t base = it.list >= 0 ? p.list[it.list + b]
+                                                          : it.io_off + ((int64_t)b << it.bits);
+                        iv.push_back({base, base + ((int64_t)1 << it.bits), 0, (int)li});
+                    }
+                    if (((int64_t)it.count << it.bits) > ((int64_t)1 << K)) {
+                        *err = "single-pass tile larger than its kernel's tile";
+                        return false;
+                    }
+                } else if (it.kind == KIND_SIGNAL_A || it.kind == KIND_SIGNAL_B) {
+                    const int CC = it.kind == KIND_SIGNAL_A ? K12_CA : K12_CB;
+                    const int L1 = K - CC, b = it.m - L1;
+                    if (!r.persistent || K != 12 || b < CC || b > K || it.bits != L1) {
+                        *err = "whole-signal item with an invalid split";
+                        return false;
+                    }
+                    if (it.ws_off < 0 || (size_t)(it.ws_off + ((int64_t)1 << it.m)) > p.ws_elems) {
+                        *err = "whole-signal item outside the workspace";
+                        return false;
+                    }
+                    const int64_t n = (int64_t)1 << it.m;
+                    iv.push_back({it.io_off, it.io_off + n, 1, (int)li});
+                    iv.push_back({it.io_off, it.io_off + n, 2, (int)li});
+                } else if (it.kind == KIND_FIRST_A || it.kind == KIND_FIRST_B) {
+                    iv.push_back({it.io_off, it.io_off + ((int64_t)1 << K), 1, (int)li});
+                } else if (it.kind == KIND_LAST) {
+                    iv.push_back({it.io_off, it.io_off + ((int64_t)it.count << it.bits), 2, (int)li});
+                    if (((int64_t)it.count << it.bits) != ((int64_t)1 << K)) {
+                        *err = "last-pass tile does not fill its kernel's tile";
+                        return false;
+                    }
+                    if (it.ws_off < 0 ||
+                        (size_t)(it.ws_off + ((int64_t)it.count << it.bits)) > p.ws_elems) {
+                        *err = "last-pass tile outside the workspace";
+                        return false;
+                    }
+                } else {
+                    *err = "unknown item kind";
+                    return false;
+                }
+            }
+        }
+        return true;
+    };
+    for (int dir = 0; dir < 2; ++dir) {
+        const std::vector<LaunchRange> &L = dir ? p.adj : p.fwd;
+        std::vector<Iv> iv;
+        if (!tile_intervals(L, iv)) return false;
+        for (int pass = 0; pass < 3; ++pass)
+            if (!check_cover(ms, off, iv, err, pass, pass > 0)) return false;
+        // per signal: covered exactly once by single, or once by first and last
+        std::vector<std::pair<int64_t, int>> starts;  // (lo, index into iv)
+        std::sort(iv.begin(), iv.end(), [](const Iv &a, const Iv &b) {
+            return a.lo != b.lo ? a.lo < b.lo : a.pass < b.pass;
+        });
+        size_t tiny_seen = 0;
+        for (size_t i = 0; i < batch; ++i) {
+            const int64_t lo = off[i], hi = off[i] + ((int64_t)1 << ms[i]);
+            // tiles starting inside the signal
+            auto first_it = std::lower_bound(iv.begin(), iv.end(), lo,
+                                             [](const Iv &a, int64_t v) { return a.lo < v; });
+            int64_t cov[3] = {0, 0, 0};
+            int first_launch = -1, last_launch = -1;
+            for (auto it = first_it; it != iv.end() && it->lo < hi; ++it) {
+                if (it->hi > hi) {
+                    *err = "tile crosses the end of signal " + std::to_string(i);
+                    return false;
+                }
+                cov[it->pass] += it->hi - it->lo;
+                if (it->pass == 1) first_launch = std::max(first_launch, it->launch);
+                if (it->pass == 2) last_launch = last_launch < 0 ? it->launch : std::min(last_launch, it->launch);
+            }
+            const int64_t n = hi - lo;
+            const bool single = cov[0] == n && cov[1] == 0 && cov[2] == 0;
+            const bool multi = cov[0] == 0 && cov[1] == n && cov[2] == n;
+            const bool tiny = cov[0] == 0 && cov[1] == 0 && cov[2] == 0;
+            if (tiny) {
+                ++tiny_seen;
+                continue;
+            }
+            if (!single && !multi) {
+                char b[200];
+                std::snprintf(b, sizeof b, "signal %zu (m=%d) covered %lld/%lld/%lld of %lld", i, ms[i],
+                              (long long)cov[0], (long long)cov[1], (long long)cov[2], (long long)n);
+                *err = b;
+                return false;
+            }
+            if (multi && L.size() > 0 && !L[0].persistent) {
+                const bool ok = dir == 0 ? first_launch < last_launch : last_launch < first_launch;
+                if (!ok) {
+                    *err = "launch order of the two passes of signal " + std::to_string(i);
+                    return false;
+                }
+            }
+        }
+        if (tiny_seen != p.tiny_off.size()) {
+            *err = "signals without tiles do not match the tiny list";
+            return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace chw

@@ -31,14 +31,16 @@ int elem_bytes(int dt)
 
 int compute_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 
-bool choose_split(int m, int dt, int forced_l1, Split *out)
+bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out)
 {
     struct Opt { int K1, CC, kind; };
-    const Opt opts[] = {{12, K12_CA, KIND_FIRST_A}, {15, K15_CA, KIND_FIRST_A},
-                        {12, K12_CB, KIND_FIRST_B}, {15, K15_CB, KIND_FIRST_B}};
-    const int kmax2 = dt == DT_F64 ? 12 : 15;
+    // preference: the widest transposed runs first (2^5 rows = 128-byte runs of
+    // FP32 in the first pass's store)
+    const Opt opts[] = {{15, K15_CA, KIND_FIRST_A}, {12, K12_CA, KIND_FIRST_A},
+                        {15, K15_CB, KIND_FIRST_B}, {12, K12_CB, KIND_FIRST_B}};
+    const int kmax2 = (dt == DT_F64 || k12_only) ? 12 : 15;
     for (const Opt &o : opts) {
-        if (o.K1 == 15 && dt == DT_F64) continue;
+        if (o.K1 == 15 && (dt == DT_F64 || k12_only)) continue;
         const int L1 = o.K1 - o.CC;
         if (forced_l1 > 0 && L1 != forced_l1) continue;
         const int b = m - L1;                 // levels left for the second pass
@@ -60,8 +62,6 @@ Item blank_item()
 {
     Item it{};
     it.list = -1;
-    it.wait_idx = -1;
-    it.done_idx = -1;
     it.count = 1;
     return it;
 }
@@ -87,11 +87,16 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     }
     const int64_t batch = (int64_t)ms.size();
     const int tiny_max = tiny_max_log2(dt);
-    const int single_max = p.cfg.single15 ? 15 : 12;
+    const bool persistent = p.cfg.exec == 2;
+    const int single_max = (p.cfg.single15 && !persistent) ? 15 : 12;
 
-    // per (K, category) item lists; category 0 BLOCKS, 1 FIRST, 2 LAST
-    std::vector<Item> cat[2][3];
+    // item lists: single-pass BLOCKS per tile size; multi-pass FIRST / LAST
+    // per chunk and tile size
     auto kidx = [](int K) { return K == 12 ? 0 : 1; };
+    std::vector<Item> blocks[2];
+    struct Chunk { std::vector<Item> first[2], last[2]; };
+    std::vector<Chunk> chunks(1);
+    int64_t chunk_fill = 0;
 
     // ---- single-pass signals, grouped by size ---------------------------
     std::vector<int64_t> order;
@@ -128,7 +133,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             it.list = (int32_t)p.list.size();
             for (size_t q = s; q < e; ++q) p.list.push_back(off[order[q]]);
         }
-        cat[kidx(K)][0].push_back(it);
+        blocks[kidx(K)].push_back(it);
         s = e;
     }
 
@@ -138,7 +143,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         const int m = ms[i];
         if (m <= single_max) continue;
         Split sp;
-        if (!choose_split(m, dt, p.cfg.split_l1, &sp))
+        if (!choose_split(m, dt, p.cfg.split_l1, persistent, &sp))
             throw std::invalid_argument("no two-pass split covers log2 size " +
                                         std::to_string(m));
         ++p.n_multi;
@@ -146,6 +151,12 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         for (const Split &q : p.splits)
             if (q.m == sp.m && q.L1 == sp.L1 && q.K1 == sp.K1 && q.K2 == sp.K2) seen = true;
         if (!seen) p.splits.push_back(sp);
+        if (p.cfg.chunk > 0 && chunk_fill > 0 && chunk_fill + ((int64_t)1 << m) > p.cfg.chunk) {
+            chunks.emplace_back();
+            chunk_fill = 0;
+        }
+        chunk_fill += (int64_t)1 << m;
+        Chunk &ch = chunks.back();
         const int L1 = sp.L1, b = m - L1;
         const int64_t rows = (int64_t)1 << b;
         for (int64_t h0 = 0; h0 < rows; h0 += (int64_t)1 << sp.CC) {
@@ -157,7 +168,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             it.h0 = (int32_t)h0;
             it.io_off = off[i] + (h0 << L1);
             it.ws_off = wsb;
-            cat[kidx(sp.K1)][1].push_back(it);
+            ch.first[kidx(sp.K1)].push_back(it);
         }
         const int bpt = 1 << (sp.K2 - b);  // blocks per last-pass tile
         const int64_t tiles = ((int64_t)1 << L1) / bpt;
@@ -169,33 +180,78 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             it.count = bpt;
             it.io_off = off[i] + (tl << sp.K2);
             it.ws_off = wsb + (tl << sp.K2);
-            cat[kidx(sp.K2)][2].push_back(it);
+            ch.last[kidx(sp.K2)].push_back(it);
         }
         wsb += (int64_t)1 << m;
     }
     p.ws_elems = (size_t)wsb;
 
-    // ---- table order: K12 {BLOCKS, FIRST, LAST}, K15 {BLOCKS, FIRST, LAST} ---
-    int start[2][3], stop[2][3];
-    for (int k = 0; k < 2; ++k)
-        for (int c = 0; c < 3; ++c) {
-            start[k][c] = (int)p.items.size();
-            p.items.insert(p.items.end(), cat[k][c].begin(), cat[k][c].end());
-            stop[k][c] = (int)p.items.size();
+    // ---- table and launch order ----------------------------------------------
+    if (persistent) {
+        // one launch; single-pass tiles and whole multi-pass signals, sorted by
+        // decreasing work (the kernel hands items out grid-stride)
+        std::vector<Item> all(blocks[0]);
+        for (const Chunk &ch : chunks)
+            for (const Item &f : ch.first[0]) {
+                if (f.h0 != 0) continue;  // one item per signal
+                Item it = blank_item();
+                it.kind = f.kind == KIND_FIRST_A ? KIND_SIGNAL_A : KIND_SIGNAL_B;
+                it.m = f.m;
+                it.bits = f.bits;          // L1
+                it.io_off = f.io_off;      // signal base (h0 = 0)
+                it.ws_off = f.ws_off;
+                all.push_back(it);
+            }
+        auto work = [](const Item &it) {
+            return (it.kind == KIND_BLOCKS) ? ((int64_t)it.count << it.bits)
+                                            : ((int64_t)2 << it.m);
+        };
+        std::stable_sort(all.begin(), all.end(),
+                         [&](const Item &x, const Item &y) { return work(x) > work(y); });
+        LaunchRange r;
+        r.K = 12;
+        r.LR = p.cfg.lr12;
+        r.persistent = 1;
+        r.begin = (int)p.items.size();
+        p.items.insert(p.items.end(), all.begin(), all.end());
+        r.end = (int)p.items.size();
+        if (p.items.size() > (size_t)0x7fffffff) throw std::bad_alloc();
+        if (r.end > r.begin) {
+            p.fwd.push_back(r);
+            p.adj.push_back(r);
         }
-    if (p.items.size() > (size_t)0x7fffffff) throw std::bad_alloc();
-    auto add = [&](std::vector<LaunchRange> &v, int k, int b, int e) {
-        if (e > b) {
-            const int K = k == 0 ? 12 : 15;
-            v.push_back(LaunchRange{K, K == 12 ? p.cfg.lr12 : p.cfg.lr15, b, e});
-        }
+        *out = std::move(p);
+        return;
+    }
+    auto append = [&](const std::vector<Item> &v, int K, LaunchRange *r) {
+        r->K = K;
+        r->LR = K == 12 ? p.cfg.lr12 : p.cfg.lr15;
+        r->begin = (int)p.items.size();
+        p.items.insert(p.items.end(), v.begin(), v.end());
+        r->end = (int)p.items.size();
+        if (p.items.size() > (size_t)0x7fffffff) throw std::bad_alloc();
     };
     for (int k = 0; k < 2; ++k) {
-        add(p.fwd[0], k, start[k][0], stop[k][1]);   // BLOCKS + FIRST
-        add(p.fwd[1], k, start[k][2], stop[k][2]);   // LAST
-        add(p.adj[0], k, start[k][0], stop[k][0]);   // BLOCKS
-        add(p.adj[0], k, start[k][2], stop[k][2]);   // LAST (adjoint first pass)
-        add(p.adj[1], k, start[k][1], stop[k][1]);   // FIRST (adjoint second pass)
+        LaunchRange r;
+        append(blocks[k], k == 0 ? 12 : 15, &r);
+        if (r.end > r.begin) {
+            p.fwd.push_back(r);
+            p.adj.push_back(r);
+        }
+    }
+    for (const Chunk &ch : chunks) {
+        LaunchRange f[2], l[2];
+        for (int k = 0; k < 2; ++k) append(ch.first[k], k == 0 ? 12 : 15, &f[k]);
+        for (int k = 0; k < 2; ++k) append(ch.last[k], k == 0 ? 12 : 15, &l[k]);
+        for (int k = 0; k < 2; ++k)
+            if (f[k].end > f[k].begin) p.fwd.push_back(f[k]);
+        for (int k = 0; k < 2; ++k)
+            if (l[k].end > l[k].begin) {
+                p.fwd.push_back(l[k]);
+                p.adj.push_back(l[k]);  // adjoint: the last pass's blocks come first
+            }
+        for (int k = 0; k < 2; ++k)
+            if (f[k].end > f[k].begin) p.adj.push_back(f[k]);
     }
     *out = std::move(p);
 }
@@ -212,8 +268,9 @@ std::string describe_plan(const BuiltPlan &p)
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
-                  "\"exec\": %d}, ",
-                  p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec);
+                  "\"exec\": %d, \"chunk\": %lld}, ",
+                  p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec,
+                  (long long)p.cfg.chunk);
     s += buf;
     s += "\"splits\": [";
     for (size_t i = 0; i < p.splits.size(); ++i) {
@@ -223,18 +280,17 @@ std::string describe_plan(const BuiltPlan &p)
         s += buf;
     }
     s += "], ";
-    auto ranges = [&](const char *name, const std::vector<LaunchRange> *ph) {
+    auto ranges = [&](const char *name, const std::vector<LaunchRange> &v) {
         s += "\"";
         s += name;
         s += "\": [";
-        bool first = true;
-        for (int f = 0; f < 2; ++f)
-            for (const LaunchRange &r : ph[f]) {
-                std::snprintf(buf, sizeof buf, "%s{\"phase\": %d, \"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d}",
-                              first ? "" : ", ", f, r.K, r.LR, r.begin, r.end);
-                s += buf;
-                first = false;
-            }
+        for (size_t i = 0; i < v.size(); ++i) {
+            const LaunchRange &r = v[i];
+            std::snprintf(buf, sizeof buf,
+                          "%s{\"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d, \"persistent\": %d}",
+                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent);
+            s += buf;
+        }
         s += "]";
     };
     ranges("forward", p.fwd);

@@ -19,14 +19,22 @@ struct PlanConfig {
     int lr15 = 5;       // register bits of the 2^15-element tile kernels (5, 6)
     int single15 = 1;   // signals with 13 <= m <= 15 in one pass of a 2^15 tile
     int split_l1 = -1;  // forced first-pass level count of multi-pass signals
-    int exec = 0;       // 0 = one launch per pass
+    int exec = 0;       // 0 = one launch per pass; 2 = one persistent launch
+                        // (2^12-element tiles, m <= 21; a workgroup runs both
+                        // passes of a multi-pass signal)
+    int64_t chunk = 0;  // elements of multi-pass signals per pass pair (0 = all):
+                        // the batch runs as first pass, last pass on each chunk
+                        // in turn, so a chunk's intermediate can stay in the
+                        // memory-side cache between its two passes
 };
 
 // Items [begin, end) of the plan's table run in one launch of the tile kernel
-// with tile bits K and register bits LR.
+// with tile bits K and register bits LR.  Launches run in list order on one
+// stream; a launch may depend on any earlier one.
 struct LaunchRange {
     int K, LR;
     int begin, end;
+    int persistent = 0;  // 1: one persistent launch over the range
 };
 
 // Two-pass split of one signal size.
@@ -40,8 +48,8 @@ struct BuiltPlan {
     std::vector<int64_t> list;        // block offsets of ragged BLOCKS items
     std::vector<int64_t> tiny_off;    // signals below one 16-byte vector
     std::vector<int32_t> tiny_m;
-    std::vector<LaunchRange> fwd[2];  // per phase (phase 1 waits for phase 0)
-    std::vector<LaunchRange> adj[2];
+    std::vector<LaunchRange> fwd;     // launches of a forward call, in order
+    std::vector<LaunchRange> adj;     // launches of a backward call, in order
     std::vector<Split> splits;        // distinct splits in use
     size_t ws_elems = 0;              // compact intermediate (compute type)
     int64_t n_single = 0, n_multi = 0, n_tiny = 0;
@@ -56,12 +64,17 @@ int compute_bytes(int dt);
 
 // Choose the two-pass split for a signal of 2^m elements; false when none of
 // the compiled variants covers m.
-bool choose_split(int m, int dt, int forced_l1, Split *out);
+bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out);
 
 // Build items and launch ranges.  Throws std::bad_alloc on allocation failure,
 // std::invalid_argument when a signal cannot be planned.
 void build_plan(const std::vector<int32_t> &m, const std::vector<int64_t> &off, int dt,
                 const PlanConfig &cfg, BuiltPlan *out);
+
+// Host-side invariants of a built plan (coverage, bounds, launch order,
+// persistent dependencies); false with a reason in *err.
+bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off, int dt,
+                const BuiltPlan &p, std::string *err);
 
 // JSON description of a built plan.
 std::string describe_plan(const BuiltPlan &p);

@@ -1,6 +1,8 @@
 // chw_registry.cpp -- merges the per-dtype kernel variant tables.
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "chw_variants.h"
 
 namespace chw {

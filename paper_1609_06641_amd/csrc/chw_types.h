@@ -21,6 +21,11 @@ enum ItemKind : int32_t {
     // Last HBM pass: blocks of 2^bits contiguous intermediate elements (the
     // remaining CHW_{m-L1} on each block), Paley-ordered store.
     KIND_LAST = 3,
+    // Persistent launch: a whole multi-pass signal (first-pass tiles with the
+    // variant-A / variant-B row count, then its last-pass tiles) run by one
+    // workgroup.
+    KIND_SIGNAL_A = 4,
+    KIND_SIGNAL_B = 5,
 };
 
 // 64-byte work item.  Offsets are element offsets:
@@ -49,10 +54,7 @@ struct Item {
     int32_t rs;         // FIRST: log2 stride of the transposed runs (m - L1)
     int32_t h0;         // FIRST: first row (of 2^L1 elements) of the tile
     int32_t m;          // log2 size of the whole signal (sets the scale)
-    int32_t wait_idx;   // persistent: counter to wait on, or -1
-    int32_t wait_target;// persistent: value the counter must reach
-    int32_t done_idx;   // persistent: counter to bump when done, or -1
-    int32_t pad_[2];
+    int32_t pad_[5];
 };
 static_assert(sizeof(Item) == 64, "Item must stay 64 bytes");
 
@@ -67,11 +69,7 @@ struct LaunchArgs {
     const int64_t *list;     // device array of block offsets (ragged BLOCKS)
     int32_t nitems;
     int32_t ortho;           // 1: scale by 2^{-m/2} at the final store
-    // persistent scheduling
-    int32_t *counters;       // device: [0] = work head, [1] = error flag,
-                             //         [2 + i] = per-item dependency counters
-    int32_t spin_limit;      // bounded wait (iterations of ~1us) before error
-    int32_t pad1;
+
 };
 
 }  // namespace chw

@@ -20,6 +20,8 @@ struct ItemsVariant {
     size_t lds_bytes;       // static LDS
     ItemsLauncher launch;
     const void *fn;         // kernel symbol (occupancy queries)
+    ItemsLauncher launch_persistent;  // persistent form (K = 12 only), or null
+    const void *fn_persistent;
 };
 
 struct TinyVariant {
@@ -35,5 +37,6 @@ const TinyVariant *find_tiny_variant(int dt, int adj);
 
 // Largest log2 size a tiny (one thread per signal) launch handles.
 constexpr int TINY_MAX_LOG2 = 3;
+
 
 }  // namespace chw

@@ -123,7 +123,9 @@ def test_describe_and_planner_properties():
     assert sp["L1"] <= sp["K1"] and 20 - sp["L1"] <= sp["K2"]
     assert p.workspace_size() == 3 * (1 << 20) * 4
     fw = plan["forward"]
-    assert {r["phase"] for r in fw} == {0, 1}
+    assert len(fw) == 2 and len(plan["backward"]) == 2   # one launch per pass
+    assert fw[0]["K"] == sp["K1"] and fw[1]["K"] == sp["K2"]
+    assert plan["backward"][0]["K"] == sp["K2"]          # adjoint: last pass first
     # first-pass items: 2^(m - L1) rows in tiles of 2^rows_log2 rows; last-pass
     # items: 2^L1 blocks of 2^(m - L1)
     rows_tiles = (1 << (20 - sp["L1"])) >> sp["rows_log2"]
@@ -159,6 +161,23 @@ def test_planner_ragged_and_options():
     assert p3.describe()["plan"]["multi"] == 2
 
 
+def test_planner_chunks():
+    # chunking: first pass then last pass for each group of signals
+    p = chw.Plan([20] * 8, dtype="f32")
+    p.set_option("chunk", 3 << 20)
+    d = p.describe()["plan"]
+    assert d["config"]["chunk"] == 3 << 20
+    fw = d["forward"]
+    assert len(fw) == 6                       # chunks of 3, 3, 2 signals
+    ends = [r["end"] - r["begin"] for r in fw]
+    assert sum(ends) == d["items"]
+    sp = d["splits"][0]
+    per_first = (1 << (20 - sp["L1"])) >> sp["rows_log2"]
+    per_last = (1 << 20) >> sp["K2"]
+    assert ends == [3 * per_first, 3 * per_last, 3 * per_first, 3 * per_last,
+                    2 * per_first, 2 * per_last]
+
+
 def test_packed_misaligned_signal_is_rejected():
     # packed back to back, 1 + 2 + 4 elements put the 8-element bf16 signal at
     # element 7: not 16-byte aligned
@@ -183,3 +202,61 @@ def test_layout_selfcheck():
     assert ok, [r for r in rep if not r.get("ok", True)]
     phases = {r["phase"] for r in rep if "phase" in r}
     assert phases == {"rounds", "contig", "paley", "transposed"}
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("opts", [dict(), dict(exec=2), dict(chunk=1 << 20), dict(single15=0),
+                                  dict(split_l1=12), dict(exec=2, lr12=5)])
+def test_plan_invariants_random_ragged(seed, opts):
+    rng = np.random.default_rng(seed)
+    hi = 22 if opts.get("exec") == 2 else 25
+    ms = rng.integers(0, hi, size=int(rng.integers(1, 40))).astype(np.int32)
+    # offsets with random aligned gaps (tiny signals may sit anywhere)
+    offs, o = [], 0
+    for k in ms:
+        o += int(rng.integers(0, 3)) * 8          # 16-byte aligned for bf16 and f32
+        offs.append(o)
+        o += max(1 << int(k), 8)
+    offs.append(o)
+    for dtype in ("f32", "bf16"):
+        try:
+            p = chw.Plan(ms, dtype=dtype, offsets=np.array(offs, dtype=np.int64))
+            for k, v in opts.items():
+                p.set_option(k, v)
+        except chw.CHWError as e:
+            # forced splits may not cover every size
+            assert opts.get("split_l1") and e.name == "CHW_ERR_UNSUPPORTED"
+            continue
+        p.check()
+        p.close()
+
+
+def test_dependency_queue_exec_is_disabled():
+    p = chw.Plan([20, 20], dtype="f32")
+    with pytest.raises(chw.CHWError) as e:
+        p.set_option("exec", 1)
+    assert e.value.name == "CHW_ERR_UNSUPPORTED"
+
+
+def test_persistent_plan_shape():
+    p = chw.Plan([20, 20, 14, 9, 9, 9], dtype="f32", persistent=True)
+    d = p.describe()["plan"]
+    assert d["config"]["exec"] == 2
+    assert len(d["forward"]) == 1 and d["forward"][0]["persistent"] == 1
+    assert d["backward"] == d["forward"]
+    # 3 whole-signal items (20, 20, 14) + 1 tile with the three 2^9 signals
+    assert d["items"] == 4 and d["multi"] == 3
+    p.check()
+
+
+def test_plan_invariants_workloads():
+    import workloads
+    ks = workloads.ragged_log2_sizes(4001)
+    offs = workloads.packed_offsets(ks)
+    for persistent in (False, True):
+        p = chw.Plan(ks, dtype="bf16", offsets=offs, persistent=persistent)
+        p.check()
+    p = chw.Plan([20] * 1024, dtype="f32")
+    p.check()
+    p = chw.Plan([24] * 16, dtype="f32")
+    p.check()

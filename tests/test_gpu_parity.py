@@ -189,7 +189,8 @@ def test_split_invariance_bitwise():
     xd = gu.dev_tensor(x, "f32")
     outs = []
     configs = [dict(), dict(lr12=5), dict(lr15=6), dict(single15=0),
-               dict(split_l1=9), dict(split_l1=10), dict(split_l1=12, lr15=6)]
+               dict(split_l1=9), dict(split_l1=10), dict(split_l1=12, lr15=6),
+               dict(split_l1=8), dict(chunk=1 << 21), dict(exec=2), dict(exec=2, lr12=5)]
     for cfg in configs:
         p = chw.Plan(sizes, dtype="f32")
         for k, v in cfg.items():
@@ -200,6 +201,15 @@ def test_split_invariance_bitwise():
         assert np.array_equal(o, outs[0]), cfg
     ref = gu.oracle_packed(x.astype(np.float64), sizes)
     assert gu.per_signal_rel(outs[0], ref, sizes).max() <= 1e-5
+
+
+@pytest.mark.skip(reason="the dependency-counter persistent kernel (exec 1) did not finish "
+                         "within 120 s on the GPU twice; cause not established, so it is "
+                         "switched off (exec 1 raises CHW_ERR_UNSUPPORTED)")
+def test_split_invariance_dependency_queue():
+    sizes = [14] * 3 + [20] * 2 + [9] * 5
+    p = chw.Plan(sizes, dtype="f32")
+    p.set_option("exec", 1)
 
 
 def test_graph_replay():
@@ -268,3 +278,45 @@ def test_streams_concurrent():
     t.cuda.synchronize()
     for o in outs:
         assert gu.per_signal_rel(gu.host_f64(o), ref, sizes).max() <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# one persistent launch (ragged batches), with graph replay
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "i32", "f64"])
+def test_persistent_ragged(dtype):
+    rng = np.random.default_rng(1234)
+    ms = rng.integers(3, 21 if dtype != "f64" else 17, size=60).astype(np.int32)
+    ms[:4] = [12, 13, 16, 20] if dtype != "f64" else [12, 13, 16, 14]
+    offs = workloads.packed_offsets(ms)
+    total = int(offs[-1])
+    norm = "none" if dtype == "i32" else "ortho"
+    if dtype == "i32":
+        x = rng.integers(-128, 128, size=total).astype(np.int32)
+    else:
+        x = rng.standard_normal(total).astype(np.float32 if dtype != "f64" else np.float64)
+    plain = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs)
+    for graph in (False, True):
+        p = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs, persistent=True, graph=graph)
+        d = p.describe()["plan"]
+        assert len(d["forward"]) == 1 and d["forward"][0]["persistent"] == 1
+        xd = gu.dev_tensor(x, dtype)
+        ws = gu.torch().empty(max(p.workspace_size(), 16), dtype=gu.torch().uint8, device="cuda")
+        outs = []
+        for rep in range(3):
+            y = p.forward(xd, workspace=ws)
+            yb = p.backward(xd, workspace=ws)
+            _sync()
+            outs.append((gu.host_f64(y), gu.host_f64(yb)))
+        ref_gpu = gu.host_f64(plain.forward(xd))
+        _sync()
+        for yf, ybk in outs:
+            assert np.array_equal(yf, ref_gpu)      # same numbers as the multi-launch path
+            assert np.array_equal(ybk, ref_gpu)     # adjoint = forward
+        xin = gu.host_f64(xd)
+        if dtype == "i32":
+            ref = gu.oracle_packed(x.astype(np.int64), ms, offs)
+            assert np.array_equal(outs[0][0].astype(np.int64), ref)
+        else:
+            ref = gu.oracle_packed(xin, ms, offs)
+            assert gu.per_signal_rel(outs[0][0], ref, ms, offs).max() <= gu.TOL[dtype]
