@@ -1,16 +1,25 @@
-"""Benchmark of the CHW transform on one MI355X.
+"""Benchmark of the CHW transform on one MI355X (gfx950).
 
-Default workload: 1024 float32 signals of 2^20 elements (orthonormal), the
-size the headline metric is quoted on; beside it, the BF16 ragged form (20000
-signals with log2 sizes in [6, 20], 2^30 elements, one graph replay).
+Headline workload: 1024 float32 signals of 2^20 elements, orthonormal
+dyadic-ordered WHT (the size the metric is quoted on).  Beside it: the BF16
+ragged form (20000 signals, log2 sizes in [6, 20], 2^30 elements, one
+persistent graph-captured launch).
 
 A step is one whole transform of the batch (every pass), inputs resident in
-HBM.  Prints ONE JSON line.
+HBM.  The timed region is bracketed by device synchronizations; rank 0 (the
+only rank) prints ONE JSON line on stdout.
+
+Other modes (not the headline line):
+  --workload NAME      profile another workload (one JSON line of its own)
+  --summarize ...      turn rocprofv3 outputs into a profiles/ summary
 """
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,10 +31,39 @@ if ROOT not in sys.path:
 
 METRIC = "CHW Gelem/s + % HBM peak, n=2^20 batch; plain FP32 vs BF16 ragged form"
 HBM_PEAK_GBS = 8000.0
+PROFILE_HEADLINE = os.path.join(ROOT, "profiles", "chw_2p20_f32.md")
+PROFILE_RAGGED = os.path.join(ROOT, "profiles", "chw_ragged_bf16.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources: a stored traffic figure is valid only for
+    the sources it was measured with."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1609_06641_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip", ".inc", ".cpp")):
+            with open(f, "rb") as fh:
+                h.update(os.path.basename(f).encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(path):
+    """Bytes per transform from a committed profile summary, or None."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_transform")
 
 
 def time_steps(fn, steps, warmup, stream):
@@ -43,6 +81,61 @@ def time_steps(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def launch_breakdown(plan, fn, steps):
+    """Per-launch durations (HIP events on the plan's stream), averaged."""
+    plan.set_option("timing", 1)
+    acc = None
+    for _ in range(steps):
+        fn()
+        t = plan.launch_times()
+        acc = np.array(t) if acc is None else acc + np.array(t)
+    plan.set_option("timing", 0)
+    return [] if acc is None else list(acc / steps)
+
+
+def roofline(elems, bytes_per_elem, launches_ms, kernel_names, traffic):
+    """Roofline of one transform: algorithmic bytes (bytes_per_elem per
+    element, one read and one write) over the transform's launch time."""
+    total_ms = float(sum(launches_ms))
+    algo = elems * bytes_per_elem
+    achieved = algo / (total_ms / 1e3) / 1e9
+    dom = int(np.argmax(launches_ms)) if launches_ms else 0
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": kernel_names[dom] if kernel_names else None,
+        "algorithmic_bytes_per_transform": algo,
+        "launches": [{"kernel": n, "ms": round(t, 4),
+                      "GBs_if_one_read_one_write": round(algo / (t / 1e3) / 1e9, 1)}
+                     for n, t in zip(kernel_names, launches_ms)],
+    }
+
+
+def configure(plan, args, x, y, ws, key="plan"):
+    """Apply --plan-config (a JSON object of planner options, or {"plan": {...},
+    "ragged": {...}}) or else run the autotuner (unless --no-tune)."""
+    if args.plan_config:
+        cfg = json.loads(args.plan_config)
+        if "plan" in cfg or "ragged" in cfg:
+            cfg = cfg.get(key, {})
+        for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk"):
+            if k in cfg:
+                plan.set_option(k, int(cfg[k]))
+    elif not args.no_tune:
+        plan.autotune(x, y, workspace=ws, iters=2)
+
+
+def launch_names(plan, direction="forward"):
+    d = plan.describe()["plan"]
+    names = []
+    if d["tiny"]:
+        names.append("chw_tiny_kernel")
+    for r in d[direction]:
+        kind = "chw_persistent_kernel" if r["persistent"] else "chw_items_kernel"
+        names.append("%s<K=%d,LR=%d> items [%d,%d)" % (kind, r["K"], r["LR"], r["begin"], r["end"]))
+    return names
+
+
 def cpu_baseline(x_host, m, sample):
     """The oracle (plain C, float64) on the first `sample` signals, all cores."""
     from oracle import c_oracle
@@ -57,42 +150,26 @@ def cpu_baseline(x_host, m, sample):
                       % (sample, x_host.shape[0], m, dt)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--tune", action="store_true", help="autotune the plan first")
-    ap.add_argument("--no-ragged", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1024)
-    ap.add_argument("--workload", default="plain_2p20_f32",
-                    help="plain_2p20_f32 (headline) or, for profiling only: "
-                         "plain_2p24_f32, precision_bf16, precision_f16, diff_f32, "
-                         "plain_small_f32, ragged_f32, ragged_bf16")
-    ap.add_argument("--copy-gib", type=float, default=0.0,
-                    help="also time a plain device copy of this many GiB (calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the batch shards across GPUs with no communication; see DESIGN.md)",
-              file=sys.stderr)
-        sys.exit(2)
+def copy_calibration(gib, dev, stream, steps):
+    """Time a plain device-to-device copy of known size (read + write bytes)."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    ms = time_steps(lambda: b.copy_(a), max(3, steps), 2, stream)
+    res = {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": round(ms, 4),
+           "GBs": round(8 * n / (ms / 1e3) / 1e9, 1)}
+    del a, b
+    return res
 
+
+# ---------------------------------------------------------------------------
+
+def bench_headline(args, dev, stream, out):
     import torch
     import workloads
     from oracle import c_oracle, metrics
     from paper_1609_06641_amd import chw
-
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-
-    if args.workload != "plain_2p20_f32":
-        run_other(args, dev, stream)
-        return
-
-    # ---- headline workload: 1024 x 2^20 float32 ------------------------------
     w = workloads.CONFIGS["plain_2p20_f32"]
     m, batch = 20, w.batch
     t0 = time.perf_counter()
@@ -101,83 +178,81 @@ def main():
     x = torch.from_numpy(x_host).to(dev)
     y = torch.empty_like(x)
     plan = chw.Plan([m] * batch, dtype="f32")
-    if args.tune:
-        plan.autotune(x, y, iters=2)
+    configure(plan, args, x, y, None)
     fwd = lambda: plan.forward(x, out=y)  # noqa: E731
     ms = time_steps(fwd, args.steps, args.warmup, stream)
     elems = batch << m
     gelem = elems / (ms / 1e3) / 1e9
-    desc = plan.describe()["plan"]
-    algo_bytes = elems * 8
-    achieved = algo_bytes / (ms / 1e3) / 1e9
-    log("plain f32: %.3f ms/step, %.1f Gelem/s, %.1f GB/s algorithmic" % (ms, gelem, achieved))
-
-    # parity spot check on sampled signals
+    launches = launch_breakdown(plan, fwd, args.steps) if not args.no_launch_timing else [ms]
+    names = launch_names(plan)
+    calls = args.warmup + args.steps * (1 if args.no_launch_timing else 2)
+    log("plain f32: %.3f ms/step, %.1f Gelem/s; launches %s" % (ms, gelem, launches))
     torch.cuda.synchronize()
     idx = [0, batch // 3, batch - 1]
     ref = c_oracle.chw_rows(x_host[idx].astype(np.float64), threads=8)
-    got = y[idx].double().cpu().numpy()
-    rel = float(np.max(metrics.rel_l2(got, ref)))
-
-    out = {
+    rel = float(np.max(metrics.rel_l2(y[idx].double().cpu().numpy(), ref)))
+    desc = plan.describe()["plan"]
+    out.update({
         "metric": METRIC, "value": round(gelem, 3), "unit": "Gelem/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "plain_2p20_f32", "batch": batch, "log2_n": m,
-                   "norm": "orthonormal", "plan": desc["config"], "splits": desc["splits"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": "whole transform (all launches of one step)",
-                     "algorithmic_bytes": algo_bytes},
+        "config": {"workload": "plain_2p20_f32: 1024 x 2^20 float32, orthonormal dyadic WHT",
+                   "batch": batch, "log2_n": m, "plan": desc["config"],
+                   "splits": desc["splits"], "autotuned": not args.no_tune},
+        "roofline": roofline(elems, 8, launches, names, stored_traffic(PROFILE_HEADLINE)),
         "parity": {"sampled_signals": idx, "max_rel_l2": rel},
-    }
+        "forward_calls": calls,
+    })
     del x, y
     torch.cuda.empty_cache()
-
-    # ---- BF16 ragged form --------------------------------------------------
-    if not args.no_ragged:
-        ks = workloads.ragged_log2_sizes(4001)
-        offs = workloads.packed_offsets(ks)
-        xr = workloads.ragged_values(4002, ks, offs)
-        xb = workloads.to_half_precision(xr, "bf16").to(dev)
-        yb = torch.empty_like(xb)
-        rp = chw.Plan(ks, dtype="bf16", offsets=offs, graph=True)
-        ws = torch.empty(max(rp.workspace_size(), 16), dtype=torch.uint8, device=dev)
-        rf = lambda: rp.forward(xb, out=yb, workspace=ws)  # noqa: E731
-        rms = time_steps(rf, args.steps, args.warmup, stream)
-        relems = int(offs[-1])
-        out["bf16_ragged"] = {"value": round(relems / (rms / 1e3) / 1e9, 3), "unit": "Gelem/s",
-                              "ms_per_step": round(rms, 4), "signals": len(ks),
-                              "elements": relems,
-                              "algorithmic_GBs": round(relems * 4 / (rms / 1e3) / 1e9, 1)}
-        log("bf16 ragged: %.3f ms/step" % rms)
-        del xb, yb, ws
-        torch.cuda.empty_cache()
-
-    if args.copy_gib > 0:
-        out["copy_calibration"] = copy_calibration(args, dev, stream)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(x_host, m, min(args.cpu_sample, batch))
-    print(json.dumps(out), flush=True)
+    return x_host, m
 
 
-def copy_calibration(args, dev, stream):
-    """Time a plain device-to-device copy of known size (read + write bytes)."""
+def bench_ragged_bf16(args, dev, stream):
     import torch
-    n = int(args.copy_gib * (1 << 30)) // 4
-    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-    b = torch.empty_like(a)
-    ms = time_steps(lambda: b.copy_(a), max(3, args.steps), 2, stream)
-    res = {"bytes_per_copy": 8 * n, "ms": round(ms, 4),
-           "GBs": round(8 * n / (ms / 1e3) / 1e9, 1)}
-    del a, b
+    import workloads
+    from oracle import c_oracle, metrics
+    from paper_1609_06641_amd import chw
+    ks = workloads.ragged_log2_sizes(4001)
+    offs = workloads.packed_offsets(ks)
+    xr = workloads.ragged_values(4002, ks, offs)
+    xb = workloads.to_half_precision(xr, "bf16").to(dev)
+    yb = torch.empty_like(xb)
+    rp = chw.Plan(ks, dtype="bf16", offsets=offs, graph=True, persistent=True)
+    ws = torch.empty(max(rp.workspace_size(), 16), dtype=torch.uint8, device=dev)
+    configure(rp, args, xb, yb, ws, key="ragged")
+    rf = lambda: rp.forward(xb, out=yb, workspace=ws)  # noqa: E731
+    rms = time_steps(rf, args.steps, args.warmup, stream)
+    relems = int(offs[-1])
+    launches = launch_breakdown(rp, rf, args.steps) if not args.no_launch_timing else [rms]
+    rp.forward(xb, out=yb, workspace=ws)   # graph replay again after timing
+    torch.cuda.synchronize()
+    # parity: a few signals of each size class
+    sel = [int(np.nonzero(ks == k)[0][0]) for k in (6, 12, 16, 20)]
+    xin = xb.double().cpu().numpy()
+    yout = yb.double().cpu().numpy()
+    rels = []
+    for i in sel:
+        n = 1 << int(ks[i])
+        ref = c_oracle.chw_batch(xin[offs[i]:offs[i] + n], [int(ks[i])])
+        rels.append(float(metrics.rel_l2(yout[offs[i]:offs[i] + n], ref)))
+    d = rp.describe()["plan"]
+    res = {"value": round(relems / (rms / 1e3) / 1e9, 3), "unit": "Gelem/s",
+           "ms_per_step": round(rms, 4), "signals": len(ks), "elements": relems,
+           "dtype": "bf16 storage, fp32 compute", "plan": d["config"],
+           "launches_per_call": len(d["forward"]),
+           "roofline": roofline(relems, 4, launches, launch_names(rp),
+                                stored_traffic(PROFILE_RAGGED)),
+           "parity": {"log2_sizes": [int(ks[i]) for i in sel], "max_rel_l2": max(rels)}}
+    log("bf16 ragged: %.3f ms/step" % rms)
+    del xb, yb, ws
+    torch.cuda.empty_cache()
     return res
 
 
 def run_other(args, dev, stream):
-    """Profiling entry for the other workloads (one JSON line, no headline)."""
+    """Profiling entry for the other workloads (one JSON line of their own)."""
     import torch
     import workloads
     from paper_1609_06641_amd import chw
@@ -188,7 +263,7 @@ def run_other(args, dev, stream):
         ks = workloads.ragged_log2_sizes(4001)
         offs = workloads.packed_offsets(ks)
         xv = torch.from_numpy(workloads.ragged_values(w.seed, ks, offs))
-        plan = chw.Plan(ks, dtype=w.dtype, offsets=offs, graph=True)
+        plan = chw.Plan(ks, dtype=w.dtype, offsets=offs, graph=True, persistent=True)
         elems = int(offs[-1])
     else:
         m = w.log2_sizes[0]
@@ -203,16 +278,158 @@ def run_other(args, dev, stream):
     x = xv.reshape(-1).to(tdt).to(dev)
     y = torch.empty_like(x)
     ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device=dev)
-    if args.tune:
-        plan.autotune(x, y, workspace=ws, iters=2)
-    ms = time_steps(lambda: plan.forward(x, out=y, workspace=ws), args.steps, args.warmup, stream)
+    configure(plan, args, x, y, ws)
+    fn = lambda: plan.forward(x, out=y, workspace=ws)  # noqa: E731
+    ms = time_steps(fn, args.steps, args.warmup, stream)
+    launches = launch_breakdown(plan, fn, args.steps) if not args.no_launch_timing else [ms]
     es = x.element_size()
     out = {"workload": w.name, "ms_per_step": round(ms, 4),
            "Gelem_s": round(elems / (ms / 1e3) / 1e9, 2),
-           "algorithmic_GBs": round(2 * es * elems / (ms / 1e3) / 1e9, 1),
-           "plan": plan.describe()["plan"]["config"]}
+           "roofline": roofline(elems, 2 * es, launches, launch_names(plan), None),
+           "plan": plan.describe()["plan"]["config"],
+           "forward_calls": args.warmup + args.steps * (1 if args.no_launch_timing else 2)}
     if args.copy_gib > 0:
-        out["copy_calibration"] = copy_calibration(args, dev, stream)
+        out["copy_calibration"] = copy_calibration(args.copy_gib, dev, stream, args.steps)
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# profile summaries
+
+def _db(path):
+    import sqlite3
+    dbs = glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True)
+    if not dbs:
+        raise SystemExit("no rocprofv3 results database under %s" % path)
+    return sqlite3.connect(dbs[0])
+
+
+def _kernel_stats(path):
+    con = _db(path)
+    rows = con.execute("select name, end - start from kernels order by start").fetchall()
+    agg = {}
+    for name, d in rows:
+        agg.setdefault(name, []).append(d / 1e3)
+    return agg
+
+
+def _counter(path, name):
+    con = _db(path)
+    rows = con.execute("select kernel_name, value from counters_collection "
+                       "where counter_name = ? order by dispatch_id", (name,)).fetchall()
+    agg = {}
+    for k, v in rows:
+        agg.setdefault(k, []).append(float(v))
+    return agg
+
+
+def summarize(args):
+    """Write a profiles/ summary from a kernel-trace run and two PMC runs.
+
+    --summarize TRACE FETCH WRITE: rocprofv3 output folders of
+      rocprofv3 --kernel-trace --stats -d TRACE -- python3 bench.py ...
+      rocprofv3 --pmc FETCH_SIZE     -d FETCH -- python3 bench.py ...
+      rocprofv3 --pmc WRITE_SIZE     -d WRITE -- python3 bench.py ...
+    The two PMC runs must time --copy-gib G of plain copy besides the
+    transform; --calls is the number of transforms each PMC run made.
+    """
+    trace_dir, fetch_dir, write_dir = args.summarize
+    stats = _kernel_stats(trace_dir)
+    fetch = _counter(fetch_dir, "FETCH_SIZE")
+    write = _counter(write_dir, "WRITE_SIZE")
+    copy_bytes = int(args.copy_gib * (1 << 30)) // 4 * 4
+    copy_name = [k for k in fetch if "copyBuffer" in k]
+    ff = fw = None
+    if copy_name:
+        cf = max(fetch[copy_name[0]])           # KiB per copy dispatch
+        cw = max(write[copy_name[0]])
+        ff = copy_bytes / 1024.0 / cf
+        fw = copy_bytes / 1024.0 / cw
+    chw_fetch = sum(sum(v) for k, v in fetch.items() if "chw::" in k)
+    chw_write = sum(sum(v) for k, v in write.items() if "chw::" in k)
+    traffic = None
+    if ff and fw and args.calls:
+        traffic = int((chw_fetch * ff + chw_write * fw) * 1024 / args.calls)
+    lines = ["# %s" % args.title, "",
+             "Kernel durations from `rocprofv3 --kernel-trace --stats` and HBM-side",
+             "bytes from two `rocprofv3 --pmc` runs (FETCH_SIZE, then WRITE_SIZE, KiB per",
+             "dispatch).  The counters are scaled by what they read for a plain",
+             "device-to-device copy of known size in the same run (%.2f GiB read and" % (copy_bytes / 2**30),
+             "written): fetch factor %s, write factor %s." % (
+                 "%.4f" % ff if ff else "n/a", "%.4f" % fw if fw else "n/a"), "",
+             "Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`):", ""]
+    for c in args.cmd or []:
+        lines.append("    " + c)
+    lines += ["", "| kernel | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for k, v in stats.items():
+        if "chw::" in k or "copyBuffer" in k:
+            lines.append("| `%s` | %d | %.1f | %.1f | %.1f |" % (k[:90], len(v), sum(v) / len(v), min(v), max(v)))
+    lines += ["", "| kernel | dispatches | FETCH_SIZE KiB avg | WRITE_SIZE KiB avg |", "|---|---|---|---|"]
+    for k in fetch:
+        if "chw::" in k or "copyBuffer" in k:
+            lines.append("| `%s` | %d | %.0f | %.0f |" % (k[:90], len(fetch[k]), sum(fetch[k]) / len(fetch[k]),
+                                                         sum(write.get(k, [0])) / max(1, len(write.get(k, [0])))))
+    summary = {"source_hash": kernel_source_hash(), "calls": args.calls,
+               "fetch_factor": ff, "write_factor": fw,
+               "traffic_bytes_per_transform": traffic,
+               "kernels_avg_us": {k[:90]: round(sum(v) / len(v), 2) for k, v in stats.items()
+                                  if "chw::" in k}}
+    lines += ["", "Machine-readable summary (the benchmark reports `traffic` from it while",
+              "`source_hash` matches the kernel sources):", "", "```json",
+              json.dumps(summary, indent=1), "```", ""]
+    text = "\n".join(lines)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--plan-config", help="JSON planner options instead of autotuning")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-launch-timing", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--workload", default="plain_2p20_f32")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also time a plain device copy of this many GiB (calibration)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
+    ap.add_argument("--calls", type=int, default=0)
+    ap.add_argument("--title", default="profile")
+    ap.add_argument("--cmd", action="append")
+    ap.add_argument("--out")
+    args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the batch shards across GPUs with no communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    if args.workload != "plain_2p20_f32":
+        run_other(args, dev, stream)
+        return
+    out = {}
+    x_host, m = bench_headline(args, dev, stream, out)
+    if not args.no_ragged:
+        out["bf16_ragged"] = bench_ragged_bf16(args, dev, stream)
+    if args.copy_gib > 0:
+        out["copy_calibration"] = copy_calibration(args.copy_gib, dev, stream, args.steps)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(x_host, m, min(args.cpu_sample, x_host.shape[0]))
     print(json.dumps(out), flush=True)
 
 

@@ -119,11 +119,13 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
                     const int64_t *offsets, chw_dtype dtype, chw_norm norm,
                     uint32_t flags);
 
-/* Bytes of device workspace a call needs (0 when every signal fits one pass,
- * or for out-of-place F32/I32/F64 calls, which route the intermediate through
- * y).  The workspace holds FP32 (FP64 for CHW_F64) intermediates between HBM
- * passes, must not be shared by concurrent calls and may be NULL when this
- * returns 0 for the call's aliasing. */
+/* Bytes of device workspace a call may need: the FP32 (FP64 for CHW_F64)
+ * intermediate between HBM passes of every signal larger than 2^12 elements.
+ * The figure does not depend on tuning or options, so a buffer sized from it
+ * stays large enough after chw_autotune / chw_plan_set_option.  Calls whose
+ * signals all run in one pass, and out-of-place forward F32/I32/F64 calls
+ * (which route the intermediate through y), accept NULL.  A workspace must
+ * not be shared by concurrent calls. */
 chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes);
 
 /*

@@ -301,7 +301,7 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
         if (ws) {
             if (reinterpret_cast<uintptr_t>(ws) & 15u)
                 return fail(CHW_ERR_MISALIGNED, "workspace must be 16-byte aligned");
-            const size_t wsb = p->built.ws_elems * (size_t)compute_bytes(p->dt);
+            const size_t wsb = p->built.ws_bound * (size_t)compute_bytes(p->dt);
             if (intervals_overlap(ws, wsb, x, bytes))
                 return fail(CHW_ERR_INVALID_ARGUMENT, "workspace overlaps x");
             if (intervals_overlap(ws, wsb, y, bytes))
@@ -473,7 +473,9 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
 chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes)
 {
     if (!plan || !bytes) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
-    *bytes = plan->built.ws_elems * (size_t)compute_bytes(plan->dt);
+    // the bound over every configuration, so that tuning or options can never
+    // need more than what a caller sized from this call
+    *bytes = plan->built.ws_bound * (size_t)compute_bytes(plan->dt);
     return CHW_OK;
 }
 
@@ -604,20 +606,31 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
                 if (m > 15 && !choose_split(m, plan->dt, l1, false, &sp)) ok = false;
             if (ok) l1s.push_back(l1);
         }
+    const bool can_persist = maxm <= 21;
     for (int lr12 : {5, 6})
         for (int lr15 : {5, 6})
             for (int s15 : {0, 1}) {
                 if (!has15 && s15 == 0) continue;
                 if (plan->dt == DT_F64 && (lr12 != 5 || lr15 != 5 || s15 != 1)) continue;
                 for (int l1 : l1s) {
-                    PlanConfig c;
+                    PlanConfig c = plan->cfg;
                     c.lr12 = lr12;
                     c.lr15 = lr15;
                     c.single15 = s15;
                     c.split_l1 = l1;
+                    c.exec = 0;
                     cands.push_back(c);
                 }
             }
+    if (can_persist)
+        for (int lr12 : {5, 6}) {
+            PlanConfig c = plan->cfg;
+            c.lr12 = lr12;
+            c.exec = 2;
+            c.split_l1 = -1;
+            if (plan->dt == DT_F64 && lr12 != 5) continue;
+            cands.push_back(c);
+        }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(CHW_ERR_HIP, "hipEventCreate failed");
@@ -641,8 +654,8 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (log_enabled())
-            std::fprintf(stderr, "[libchw] tune lr12=%d lr15=%d single15=%d split_l1=%d: %.4f ms\n",
-                         c.lr12, c.lr15, c.single15, c.split_l1, ms / iters);
+            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d: %.4f ms\n",
+                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, ms / iters);
         if (ms < best_ms) {
             best_ms = ms;
             best = c;

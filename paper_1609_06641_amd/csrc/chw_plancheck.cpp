@@ -52,6 +52,10 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
 {
     (void)dt;
     const size_t batch = ms.size();
+    if (p.ws_elems > p.ws_bound) {
+        *err = "configuration workspace exceeds the reported bound";
+        return false;
+    }
     // classify signals exactly as the plan did: a signal is multi-pass iff it
     // has first-pass tiles
     auto tile_intervals = [&](const std::vector<LaunchRange> &launches, std::vector<Iv> &iv) {

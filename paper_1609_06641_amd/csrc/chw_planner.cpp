@@ -185,6 +185,12 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         wsb += (int64_t)1 << m;
     }
     p.ws_elems = (size_t)wsb;
+    // every configuration runs a subset of the signals above 2^12 in two passes,
+    // so this bounds the workspace of all of them (the size a caller allocates
+    // must not change when the plan is tuned)
+    for (int64_t i = 0; i < batch; ++i)
+        if (ms[i] > 12) p.ws_bound += (size_t)1 << ms[i];
+    if (p.ws_elems > p.ws_bound) throw std::logic_error("workspace bound");
 
     // ---- table and launch order ----------------------------------------------
     if (persistent) {

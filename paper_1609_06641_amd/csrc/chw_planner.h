@@ -51,7 +51,8 @@ struct BuiltPlan {
     std::vector<LaunchRange> fwd;     // launches of a forward call, in order
     std::vector<LaunchRange> adj;     // launches of a backward call, in order
     std::vector<Split> splits;        // distinct splits in use
-    size_t ws_elems = 0;              // compact intermediate (compute type)
+    size_t ws_elems = 0;              // compact intermediate of this configuration
+    size_t ws_bound = 0;              // intermediate bound over every configuration
     int64_t n_single = 0, n_multi = 0, n_tiny = 0;
 };
 

@@ -231,6 +231,25 @@ def test_plan_invariants_random_ragged(seed, opts):
         p.close()
 
 
+@pytest.mark.parametrize("sizes", [[14] * 8, [12] * 4 + [13, 15], [20, 9, 16], [6] * 5])
+def test_workspace_size_does_not_depend_on_options(sizes):
+    # Regression: the workspace a caller allocates from chw_workspace_size()
+    # must cover every configuration the autotuner or options may switch to
+    # (single-pass signals of 2^13..2^15 may be moved to two passes).
+    base = chw.Plan(sizes, dtype="f32")
+    ws0 = base.workspace_size()
+    assert ws0 == 4 * sum(1 << k for k in sizes if k > 12)
+    for opts in (dict(single15=0), dict(exec=2), dict(split_l1=9), dict(lr15=6, single15=0)):
+        p = chw.Plan(sizes, dtype="f32")
+        try:
+            for k, v in opts.items():
+                p.set_option(k, v)
+        except chw.CHWError:
+            continue
+        assert p.workspace_size() == ws0
+        p.check()
+
+
 def test_dependency_queue_exec_is_disabled():
     p = chw.Plan([20, 20], dtype="f32")
     with pytest.raises(chw.CHWError) as e:

@@ -261,6 +261,23 @@ def test_unnormalized_float():
     assert np.array_equal(gu.host_f64(y), ref.astype(np.float64))  # exact: |y| < 2^24
 
 
+def test_autotune_with_caller_sized_workspace():
+    # Regression: tuning may move 2^14 signals from one pass to two; the
+    # workspace sized from workspace_size() before tuning must cover that.
+    t = gu.torch()
+    sizes = [14] * 8
+    x = workloads.float_signals(950, 8, 14).reshape(-1)
+    p = chw.Plan(sizes, dtype="f32")
+    ws = t.empty(max(p.workspace_size(), 16), dtype=t.uint8, device="cuda")
+    xd = gu.dev_tensor(x, "f32")
+    y = t.empty_like(xd)
+    p.autotune(xd, y, workspace=ws, iters=1)
+    p.forward(xd, out=y, workspace=ws)
+    _sync()
+    ref = gu.oracle_packed(x.astype(np.float64), sizes)
+    assert gu.per_signal_rel(gu.host_f64(y), ref, sizes).max() <= 1e-5
+
+
 def test_streams_concurrent():
     t = gu.torch()
     sizes = [18] * 2
