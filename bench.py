@@ -118,7 +118,7 @@ def configure(plan, args, x, y, ws, key="plan"):
         cfg = json.loads(args.plan_config)
         if "plan" in cfg or "ragged" in cfg:
             cfg = cfg.get(key, {})
-        for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk"):
+        for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk", "stream"):
             if k in cfg:
                 plan.set_option(k, int(cfg[k]))
     elif not args.no_tune:
@@ -130,9 +130,15 @@ def launch_names(plan, direction="forward"):
     names = []
     if d["tiny"]:
         names.append("chw_tiny_kernel")
+    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST"}
     for r in d[direction]:
-        kind = "chw_persistent_kernel" if r["persistent"] else "chw_items_kernel"
-        names.append("%s<K=%d,LR=%d> items [%d,%d)" % (kind, r["K"], r["LR"], r["begin"], r["end"]))
+        if r["persistent"]:
+            kind = "chw_persistent_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])
+        elif r.get("stream"):
+            kind = "chw_stream_kernel<K=%d,LR=%d,%s>" % (r["K"], r["LR"], kinds[r["stream"]])
+        else:
+            kind = "chw_items_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])
+        names.append("%s items [%d,%d)" % (kind, r["begin"], r["end"]))
     return names
 
 

@@ -163,6 +163,10 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               tiles; signals up to 2^21; also set by CHW_FLAG_PERSISTENT).
  *               1 (a dependency-counter work queue) is disabled: it gives
  *               CHW_ERR_UNSUPPORTED.
+ *   "stream"    1 (default): a launch (exec 0) of 2^15-element tiles that
+ *               are all full and of one kind runs as a loop over its items,
+ *               fetching the next tile's vectors while the current tile runs;
+ *               0: one workgroup per tile.
  *   "timing"    1: record a HIP event around every launch (instrumentation;
  *               may be toggled at any time; disables graph replay)
  * Unknown keys or values give CHW_ERR_INVALID_ARGUMENT; so does changing a
@@ -180,8 +184,8 @@ chw_status chw_launch_times(chw_plan_t plan, float *ms, int *n);
 /* Host-only check of the plan's work tables: every element of every signal is
  * covered exactly once per pass (one single-pass tile, or one first-pass and
  * one last-pass tile), no tile leaves its signal or the workspace, launches of
- * the two passes are ordered, and persistent whole-signal items fit the tile
- * sizes.  CHW_OK, or
+ * the two passes are ordered, persistent whole-signal items fit the tile
+ * sizes, and prefetching launches hold only full tiles of one kind.  CHW_OK, or
  * CHW_ERR_UNSUPPORTED with the reason in chw_last_error(). */
 chw_status chw_plan_check(chw_plan_t plan);
 

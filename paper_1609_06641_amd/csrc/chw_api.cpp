@@ -254,13 +254,14 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         a.items = ds.items + r.begin;
         a.nitems = r.end - r.begin;
         hipError_t e;
-        if (r.persistent) {
-            int &cap = ds.grid_cap[v->fn_persistent];
+        // resident workgroups of a looping kernel on this device
+        auto grid_cap = [&](const void *fn) {
+            int &cap = ds.grid_cap[fn];
             if (cap == 0) {
                 int per_cu = 0, dev = 0;
                 (void)hipGetDevice(&dev);
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->fn_persistent, v->nt, 0);
-                if (e != hipSuccess || per_cu < 1) {
+                hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, v->nt, 0);
+                if (oe != hipSuccess || per_cu < 1) {
                     (void)hipGetLastError();
                     per_cu = 1;
                 }
@@ -268,7 +269,13 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
                 (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
                 cap = per_cu * std::max(1, cus);
             }
-            e = v->launch_persistent(dim3(std::min(a.nitems, cap)), stream, a);
+            return cap;
+        };
+        if (r.persistent) {
+            e = v->launch_persistent(dim3(std::min(a.nitems, grid_cap(v->fn_persistent))), stream, a);
+        } else if (r.stream >= 1 && r.stream <= 4) {
+            const void *fn = v->fn_stream[r.stream - 1];
+            e = v->launch_stream[r.stream - 1](dim3(std::min(a.nitems, grid_cap(fn))), stream, a);
         } else {
             e = v->launch(dim3(a.nitems), stream, a);
         }
@@ -528,6 +535,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
                     "exec 1 (dependency-counter work queue) is disabled in this build");
     else if (k == "exec" && (value == 0 || value == 2)) cfg.exec = (int)value;
     else if (k == "chunk" && value >= 0) cfg.chunk = value;
+    else if (k == "stream" && (value == 0 || value == 1)) cfg.stream = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
     return rebuild(plan, cfg);
 }
@@ -599,7 +607,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
     }
     std::vector<int> l1s = {-1};
     if (has_multi)
-        for (int l1 : {8, 9, 10, 12}) {
+        for (int l1 : {15 - K15_CA, 12 - K12_CA, 15 - K15_CB, 12 - K12_CB}) {
             Split sp;
             bool ok = true;
             for (int32_t m : plan->m)
@@ -612,15 +620,17 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             for (int s15 : {0, 1}) {
                 if (!has15 && s15 == 0) continue;
                 if (plan->dt == DT_F64 && (lr12 != 5 || lr15 != 5 || s15 != 1)) continue;
-                for (int l1 : l1s) {
-                    PlanConfig c = plan->cfg;
-                    c.lr12 = lr12;
-                    c.lr15 = lr15;
-                    c.single15 = s15;
-                    c.split_l1 = l1;
-                    c.exec = 0;
-                    cands.push_back(c);
-                }
+                for (int l1 : l1s)
+                    for (int stream_mode : {0, 1}) {
+                        PlanConfig c = plan->cfg;
+                        c.lr12 = lr12;
+                        c.lr15 = lr15;
+                        c.single15 = s15;
+                        c.split_l1 = l1;
+                        c.exec = 0;
+                        c.stream = stream_mode;
+                        cands.push_back(c);
+                    }
             }
     if (can_persist)
         for (int lr12 : {5, 6}) {
@@ -628,6 +638,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             c.lr12 = lr12;
             c.exec = 2;
             c.split_l1 = -1;
+            c.stream = 0;
             if (plan->dt == DT_F64 && lr12 != 5) continue;
             cands.push_back(c);
         }
@@ -654,8 +665,8 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (log_enabled())
-            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d: %.4f ms\n",
-                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, ms / iters);
+            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d stream=%d: %.4f ms\n",
+                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, c.stream, ms / iters);
         if (ms < best_ms) {
             best_ms = ms;
             best = c;

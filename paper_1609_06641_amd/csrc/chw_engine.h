@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "chw_layout.h"
 #include "chw_types.h"
 
@@ -40,45 +42,80 @@ template <> struct Types<DT_F64>  { using S = double;   using C = double; };
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Every global access of the tile phases is one 16-byte vector.  Each element
+// is read once and written once per HBM pass, so by default the accesses carry
+// the non-temporal (streaming) hint; the three roles (input reads, output
+// writes, intermediate reads and writes) can be switched separately.
+#ifndef CHW_NT_IN
+#define CHW_NT_IN 1
+#endif
+#ifndef CHW_NT_OUT
+#define CHW_NT_OUT 1
+#endif
+#ifndef CHW_NT_INTER
+#define CHW_NT_INTER 1
+#endif
+
+template <bool NT, typename P>
+__device__ __forceinline__ u32x4 ld16(const P *p)
+{
+    const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+
+template <bool NT, typename P>
+__device__ __forceinline__ void st16(P *p, u32x4 v)
+{
+    u32x4 *q = reinterpret_cast<u32x4 *>(p);
+    if constexpr (NT) __builtin_nontemporal_store(v, q);
+    else *q = v;
+}
+
+// Vec<T>: V elements of storage type T per 16-byte vector; decode widens to
+// the compute type, encode narrows from it.
 template <typename T> struct Vec;
 
 template <> struct Vec<float> {
     static constexpr int V = 4;
-    static __device__ __forceinline__ void load(const float *p, float *o)
+    static __device__ __forceinline__ void decode(u32x4 r, float *o)
     {
-        float4 q = *reinterpret_cast<const float4 *>(p);
-        o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = __uint_as_float(r[i]);
     }
-    static __device__ __forceinline__ void store(float *p, const float *v)
+    static __device__ __forceinline__ u32x4 encode(const float *v)
     {
-        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        return u32x4{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                     __float_as_uint(v[3])};
     }
 };
 
 template <> struct Vec<uint32_t> {
     static constexpr int V = 4;
-    static __device__ __forceinline__ void load(const uint32_t *p, uint32_t *o)
+    static __device__ __forceinline__ void decode(u32x4 r, uint32_t *o)
     {
-        uint4 q = *reinterpret_cast<const uint4 *>(p);
-        o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = r[i];
     }
-    static __device__ __forceinline__ void store(uint32_t *p, const uint32_t *v)
+    static __device__ __forceinline__ u32x4 encode(const uint32_t *v)
     {
-        *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+        return u32x4{v[0], v[1], v[2], v[3]};
     }
 };
 
 template <> struct Vec<double> {
     static constexpr int V = 2;
-    static __device__ __forceinline__ void load(const double *p, double *o)
+    static __device__ __forceinline__ void decode(u32x4 r, double *o)
     {
-        double2 q = *reinterpret_cast<const double2 *>(p);
-        o[0] = q.x; o[1] = q.y;
+        o[0] = __builtin_bit_cast(double, (uint64_t)r[0] | ((uint64_t)r[1] << 32));
+        o[1] = __builtin_bit_cast(double, (uint64_t)r[2] | ((uint64_t)r[3] << 32));
     }
-    static __device__ __forceinline__ void store(double *p, const double *v)
+    static __device__ __forceinline__ u32x4 encode(const double *v)
     {
-        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+        const uint64_t a = __builtin_bit_cast(uint64_t, v[0]), b = __builtin_bit_cast(uint64_t, v[1]);
+        return u32x4{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
     }
 };
 
@@ -86,55 +123,56 @@ template <> struct Vec<double> {
 // narrowing rounds to nearest even (v_cvt_pk_bf16_f32).
 template <> struct Vec<bf16s> {
     static constexpr int V = 8;
-    static __device__ __forceinline__ void load(const bf16s *p, float *o)
+    static __device__ __forceinline__ void decode(u32x4 r, float *o)
     {
-        uint4 q = *reinterpret_cast<const uint4 *>(p);
-        uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            o[2 * i] = __uint_as_float(w[i] << 16);
-            o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+            o[2 * i] = __uint_as_float(r[i] << 16);
+            o[2 * i + 1] = __uint_as_float(r[i] & 0xffff0000u);
         }
     }
-    static __device__ __forceinline__ void store(bf16s *p, const float *v)
+    static __device__ __forceinline__ u32x4 encode(const float *v)
     {
-        uint32_t w[4];
+        u32x4 w;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             f32x2 f = {v[2 * i], v[2 * i + 1]};
             bf16x2 h = __builtin_convertvector(f, bf16x2);
             w[i] = __builtin_bit_cast(uint32_t, h);
         }
-        *reinterpret_cast<uint4 *>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+        return w;
     }
 };
 
 // float16: widening is exact; narrowing rounds to nearest even.
 template <> struct Vec<f16s> {
     static constexpr int V = 8;
-    static __device__ __forceinline__ void load(const f16s *p, float *o)
+    static __device__ __forceinline__ void decode(u32x4 r, float *o)
     {
-        uint4 q = *reinterpret_cast<const uint4 *>(p);
-        uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            f16x2 h = __builtin_bit_cast(f16x2, w[i]);
+            f16x2 h = __builtin_bit_cast(f16x2, (uint32_t)r[i]);
             o[2 * i] = (float)h.x;
             o[2 * i + 1] = (float)h.y;
         }
     }
-    static __device__ __forceinline__ void store(f16s *p, const float *v)
+    static __device__ __forceinline__ u32x4 encode(const float *v)
     {
-        uint32_t w[4];
+        u32x4 w;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             f32x2 f = {v[2 * i], v[2 * i + 1]};
             f16x2 h = __builtin_convertvector(f, f16x2);
             w[i] = __builtin_bit_cast(uint32_t, h);
         }
-        *reinterpret_cast<uint4 *>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+        return w;
     }
 };
+
+template <bool NT, typename T, typename C>
+__device__ __forceinline__ void vload(const T *p, C *o) { Vec<T>::decode(ld16<NT>(p), o); }
+template <bool NT, typename T, typename C>
+__device__ __forceinline__ void vstore(T *p, const C *v) { st16<NT>(p, Vec<T>::encode(v)); }
 
 // Orthonormal factor 2^{-m/2}: exact power of two, times fl(2^{-1/2}) when m
 // is odd.
@@ -164,6 +202,7 @@ struct Engine {
     using S = typename Types<DT>::S;
     using C = typename Types<DT>::C;
     static constexpr int N = L::N, NT = L::NT, R = L::R, J = L::J;
+    static constexpr bool NT_IN = CHW_NT_IN, NT_OUT = CHW_NT_OUT, NT_INTER = CHW_NT_INTER;
     static_assert(CA >= 2 && CB >= 2 && CA < K && CB < K, "first-pass row counts");
 
     // ---- butterflies -------------------------------------------------------
@@ -223,7 +262,7 @@ struct Engine {
     // Tile element e <-> memory element (block e >> bits at its base) + (e &
     // (2^bits - 1)).  Blocks are consecutive from `off` unless `list` gives
     // their bases.  Only the first `count` blocks exist.
-    template <typename T>
+    template <bool H, typename T>
     static __device__ __forceinline__ void load_contig(C *lds, const T *src, int64_t off,
                                                        int bits, int count,
                                                        const int64_t *list, int t)
@@ -236,7 +275,7 @@ struct Engine {
         if (full) {
             const T *s = src + off + V * t;
 #pragma unroll
-            for (int k = 0; k < NV; ++k) Vec<T>::load(s + V * NT * k, vals[k]);
+            for (int k = 0; k < NV; ++k) vload<H>(s + V * NT * k, vals[k]);
 #pragma unroll
             for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -249,7 +288,7 @@ struct Engine {
                 const int blk = e0 >> bits;
                 if (blk < count) {
                     const int64_t g = list ? list[blk] + (e0 & mask) : off + e0;
-                    Vec<T>::load(src + g, vals[k]);
+                    vload<H>(src + g, vals[k]);
 #pragma unroll
                     for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[k][u];
                 }
@@ -257,7 +296,7 @@ struct Engine {
         }
     }
 
-    template <typename T>
+    template <bool H, typename T>
     static __device__ __forceinline__ void store_contig(const C *lds, T *dst, int64_t off,
                                                         int bits, int count,
                                                         const int64_t *list, int t,
@@ -279,16 +318,27 @@ struct Engine {
                     if (do_scale) vals[u] = scale_mul(vals[u], scale);
                 }
                 const int64_t g = (!full && list) ? list[blk] + (e0 & mask) : off + e0;
-                Vec<T>::store(dst + g, vals);
+                vstore<H>(dst + g, vals);
             }
         }
     }
 
     // ---- Paley-order phases --------------------------------------------------
+    // brev_low(x, bits) reverses bits [0, bits) of x and keeps the others: a
+    // bit permutation, so for the disjoint thread / iteration / lane fields of
+    // an output position o = V t | V NT k | u the tile element is
+    // brev_low(V t) | brev_low(V NT k) | brev_low(u), and its padded LDS word is
+    // the sum of the three padded parts (the last two are wave-uniform).
+    static __device__ __forceinline__ int brev_low(int x, int bits)
+    {
+        const int mask = (1 << bits) - 1;
+        return (x & ~mask) | (int)rbrev((uint32_t)(x & mask), bits);
+    }
+
     // Memory position (blk << bits) | p holds tile element (blk << bits) |
     // bitrev_bits(p): the dyadic order of eq. (1) is the natural radix-2 order
     // read at bit-reversed positions.
-    template <typename T>
+    template <bool H, typename T>
     static __device__ __forceinline__ void store_paley(const C *lds, T *dst, int64_t off,
                                                        int bits, int count,
                                                        const int64_t *list, int t,
@@ -306,31 +356,35 @@ struct Engine {
                     vals[u] = lb[L::pad((int)cbrev((uint32_t)(V * NT * k + u), K))];
                     if (do_scale) vals[u] = scale_mul(vals[u], scale);
                 }
-                Vec<T>::store(d + V * NT * k, vals);
+                vstore<H>(d + V * NT * k, vals);
             }
         } else {
             const int mask = (1 << bits) - 1;
+            const C *lb = lds + L::pad(brev_low(V * t, bits));
+            int ul[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) ul[u] = L::pad(brev_low(u, bits));
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 const int o0 = V * t + V * NT * k;
                 const int blk = o0 >> bits;
                 if (blk < count) {
                     const int p0 = o0 & mask;
+                    const int kl = L::pad(brev_low(V * NT * k, bits));
                     C vals[V];
 #pragma unroll
                     for (int u = 0; u < V; ++u) {
-                        const int e = (blk << bits) | (int)rbrev((uint32_t)(p0 + u), bits);
-                        vals[u] = lds[L::pad(e)];
+                        vals[u] = lb[kl + ul[u]];
                         if (do_scale) vals[u] = scale_mul(vals[u], scale);
                     }
                     const int64_t g = list ? list[blk] + p0 : off + o0;
-                    Vec<T>::store(dst + g, vals);
+                    vstore<H>(dst + g, vals);
                 }
             }
         }
     }
 
-    template <typename T>
+    template <bool H, typename T>
     static __device__ __forceinline__ void load_paley(C *lds, const T *src, int64_t off,
                                                       int bits, int count,
                                                       const int64_t *list, int t)
@@ -341,7 +395,7 @@ struct Engine {
             C *lb = lds + L::pad((int)rbrev((uint32_t)(V * t), K));
             const T *s = src + (list ? list[0] : off) + V * t;
 #pragma unroll
-            for (int k = 0; k < NV; ++k) Vec<T>::load(s + V * NT * k, vals[k]);
+            for (int k = 0; k < NV; ++k) vload<H>(s + V * NT * k, vals[k]);
 #pragma unroll
             for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -349,6 +403,10 @@ struct Engine {
                     lb[L::pad((int)cbrev((uint32_t)(V * NT * k + u), K))] = vals[k][u];
         } else {
             const int mask = (1 << bits) - 1;
+            C *lb = lds + L::pad(brev_low(V * t, bits));
+            int ul[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) ul[u] = L::pad(brev_low(u, bits));
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 const int o0 = V * t + V * NT * k;
@@ -356,12 +414,10 @@ struct Engine {
                 if (blk < count) {
                     const int p0 = o0 & mask;
                     const int64_t g = list ? list[blk] + p0 : off + o0;
-                    Vec<T>::load(src + g, vals[k]);
+                    vload<H>(src + g, vals[k]);
+                    const int kl = L::pad(brev_low(V * NT * k, bits));
 #pragma unroll
-                    for (int u = 0; u < V; ++u) {
-                        const int e = (blk << bits) | (int)rbrev((uint32_t)(p0 + u), bits);
-                        lds[L::pad(e)] = vals[k][u];
-                    }
+                    for (int u = 0; u < V; ++u) lb[kl + ul[u]] = vals[k][u];
                 }
             }
         }
@@ -379,14 +435,15 @@ struct Engine {
         constexpr int V = Vec<C>::V, NV = N / (V * NT);
         static_assert(V <= (1 << CC), "a vector must stay inside one run");
         const C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
-        C *d = dst + base + h0 + L::template transp_goff<CC>(V * t, rs);
+        C *d = dst + base + h0 + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), rs);
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             C vals[V];
 #pragma unroll
             for (int u = 0; u < V; ++u)
                 vals[u] = lb[L::pad(L::template transp_e<V, CC>(0, k, u))];
-            Vec<C>::store(d + L::template transp_goff<CC>(V * NT * k, rs), vals);
+            st16<NT_INTER>(d + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(NT * k), rs),
+                           Vec<C>::encode(vals));
         }
     }
 
@@ -397,11 +454,11 @@ struct Engine {
         constexpr int V = Vec<C>::V, NV = N / (V * NT);
         static_assert(V <= (1 << CC), "a vector must stay inside one run");
         C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
-        const C *s = src + base + h0 + L::template transp_goff<CC>(V * t, rs);
+        const C *s = src + base + h0 + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), rs);
         C vals[NV][V];
 #pragma unroll
         for (int k = 0; k < NV; ++k)
-            Vec<C>::load(s + L::template transp_goff<CC>(V * NT * k, rs), vals[k]);
+            vload<NT_INTER>(s + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(NT * k), rs), vals[k]);
 #pragma unroll
         for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -410,24 +467,84 @@ struct Engine {
     }
 
     // ---- one work item -------------------------------------------------------
-    template <int CC, bool ADJ>
-    static __device__ __forceinline__ void first_item(const Item &it, const LaunchArgs &a,
-                                                      C *lds, int t)
+    // run_item = load_item, barrier, finish_item.  load_item stages the tile in
+    // LDS; finish_item runs the tile's stages and its store phase.
+    template <int CC>
+    static __device__ __forceinline__ int64_t first_base(const Item &it, const LaunchArgs &a)
     {
-        constexpr int L1 = K - CC;
+        return a.inter_is_io ? it.io_off - ((int64_t)it.h0 << (K - CC)) : it.ws_off;
+    }
+    static __device__ __forceinline__ int64_t last_base(const Item &it, const LaunchArgs &a)
+    {
+        return a.inter_is_io ? it.io_off : it.ws_off;
+    }
+
+    template <bool ADJ>
+    static __device__ __forceinline__ void load_item(const Item &it, const LaunchArgs &a,
+                                                     C *lds, int t)
+    {
+        const S *in = static_cast<const S *>(a.in);
+        const C *inter = static_cast<const C *>(a.inter);
+        switch (it.kind) {
+        case KIND_BLOCKS: {
+            const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t);
+            else load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t);
+            break;
+        }
+        case KIND_FIRST_A:
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
+            else load_transp<CA>(lds, inter, first_base<CA>(it, a), it.h0, it.rs, t);
+            break;
+        case KIND_FIRST_B:
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
+            else load_transp<CB>(lds, inter, first_base<CB>(it, a), it.h0, it.rs, t);
+            break;
+        case KIND_LAST:
+            if constexpr (!ADJ) load_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t);
+            else load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, nullptr, t);
+            break;
+        default:
+            break;
+        }
+    }
+
+    // stages and store phase of one item of a kind known at compile time
+    template <bool ADJ, int KIND>
+    static __device__ __forceinline__ void finish_kind(const Item &it, const LaunchArgs &a,
+                                                       C *lds, int t)
+    {
+        S *out = static_cast<S *>(a.out);
         C *inter = static_cast<C *>(a.inter);
-        const int64_t base = a.inter_is_io ? it.io_off - ((int64_t)it.h0 << L1) : it.ws_off;
-        if constexpr (!ADJ) {
-            load_contig<S>(lds, static_cast<const S *>(a.in), it.io_off, K, 1, nullptr, t);
-            __syncthreads();
-            rounds<false>(lds, L1, t);
-            store_transp<CC>(lds, inter, base, it.h0, it.rs, t);
+        const C sc = ortho_scale<C>(it.m);
+        const bool ortho = a.ortho != 0;
+        if constexpr (KIND == KIND_BLOCKS) {
+            const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
+            rounds<ADJ>(lds, it.bits, t);
+            if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
+            else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
+        } else if constexpr (KIND == KIND_FIRST_A || KIND == KIND_FIRST_B) {
+            constexpr int CC = KIND == KIND_FIRST_A ? CA : CB;
+            rounds<ADJ>(lds, K - CC, t);
+            if constexpr (!ADJ) store_transp<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
+            else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho);
         } else {
-            load_transp<CC>(lds, inter, base, it.h0, it.rs, t);
-            __syncthreads();
-            rounds<true>(lds, L1, t);
-            store_contig<S>(lds, static_cast<S *>(a.out), it.io_off, K, 1, nullptr, t,
-                            ortho_scale<C>(it.m), a.ortho != 0);
+            rounds<ADJ>(lds, it.bits, t);
+            if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, nullptr, t, sc, ortho);
+            else store_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t, C(1), false);
+        }
+    }
+
+    template <bool ADJ>
+    static __device__ __forceinline__ void finish_item(const Item &it, const LaunchArgs &a,
+                                                       C *lds, int t)
+    {
+        switch (it.kind) {
+        case KIND_BLOCKS: finish_kind<ADJ, KIND_BLOCKS>(it, a, lds, t); break;
+        case KIND_FIRST_A: finish_kind<ADJ, KIND_FIRST_A>(it, a, lds, t); break;
+        case KIND_FIRST_B: finish_kind<ADJ, KIND_FIRST_B>(it, a, lds, t); break;
+        case KIND_LAST: finish_kind<ADJ, KIND_LAST>(it, a, lds, t); break;
+        default: break;
         }
     }
 
@@ -435,52 +552,109 @@ struct Engine {
     static __device__ __forceinline__ void run_item(const Item &it, const LaunchArgs &a,
                                                     C *lds, int t)
     {
-        switch (it.kind) {
-        case KIND_BLOCKS: {
-            const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
-            if constexpr (!ADJ) {
-                load_contig<S>(lds, static_cast<const S *>(a.in), it.io_off, it.bits,
-                               it.count, list, t);
-                __syncthreads();
-                rounds<false>(lds, it.bits, t);
-                store_paley<S>(lds, static_cast<S *>(a.out), it.io_off, it.bits, it.count,
-                               list, t, ortho_scale<C>(it.m), a.ortho != 0);
-            } else {
-                load_paley<S>(lds, static_cast<const S *>(a.in), it.io_off, it.bits,
-                              it.count, list, t);
-                __syncthreads();
-                rounds<true>(lds, it.bits, t);
-                store_contig<S>(lds, static_cast<S *>(a.out), it.io_off, it.bits, it.count,
-                                list, t, ortho_scale<C>(it.m), a.ortho != 0);
+        load_item<ADJ>(it, a, lds, t);
+        __syncthreads();
+        finish_item<ADJ>(it, a, lds, t);
+    }
+
+    // ---- prefetching (streaming) form ------------------------------------------
+    // A launch whose items are all full tiles of one kind (no block lists) can
+    // fetch the next item's 16-byte vectors into registers while the current
+    // item runs its stages and stores.  The tile's source is either the input
+    // (storage type S) or the intermediate (compute type C):
+    //   forward BLOCKS / FIRST : input, contiguous        -> LDS contiguous
+    //   forward LAST           : intermediate, contiguous -> LDS contiguous
+    //   adjoint BLOCKS / LAST  : input, contiguous        -> LDS Paley positions
+    //   adjoint FIRST          : intermediate, transposed -> LDS transposed
+    // and the LDS placement is exactly the one of load_item.  Global addresses
+    // are a uniform base per vector iteration plus one 32-bit per-thread offset.
+    template <bool ADJ, int KIND>
+    static constexpr bool src_inter()
+    {
+        return ADJ ? (KIND == KIND_FIRST_A || KIND == KIND_FIRST_B) : KIND == KIND_LAST;
+    }
+    template <bool ADJ, int KIND>
+    using SrcT = typename std::conditional<src_inter<ADJ, KIND>(), C, S>::type;
+    template <bool ADJ, int KIND>
+    static constexpr int nraw() { return N / (Vec<SrcT<ADJ, KIND>>::V * NT); }
+
+    template <bool ADJ, int KIND>
+    static __device__ __forceinline__ void stream_fetch(const Item &it, const LaunchArgs &a,
+                                                        u32x4 *raw, int t)
+    {
+        using T = SrcT<ADJ, KIND>;
+        constexpr int V = Vec<T>::V, NV = nraw<ADJ, KIND>();
+        if constexpr (ADJ && src_inter<ADJ, KIND>()) {
+            constexpr int CC = KIND == KIND_FIRST_A ? CA : CB;
+            const C *base = static_cast<const C *>(a.inter) + first_base<CC>(it, a) + it.h0;
+            const uint32_t toff =
+                (uint32_t)L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), it.rs);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const C *pk = base + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(NT * k), it.rs);
+                raw[k] = ld16<NT_INTER>(pk + toff);
             }
-            break;
+        } else {
+            const T *base;
+            if constexpr (src_inter<ADJ, KIND>()) base = static_cast<const C *>(a.inter) + last_base(it, a);
+            else base = static_cast<const S *>(a.in) + it.io_off;
+            const uint32_t toff = (uint32_t)(V * t);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) raw[k] = ld16<src_inter<ADJ, KIND>() ? NT_INTER : NT_IN>(base + V * NT * k + toff);
         }
-        case KIND_FIRST_A:
-            first_item<CA, ADJ>(it, a, lds, t);
-            break;
-        case KIND_FIRST_B:
-            first_item<CB, ADJ>(it, a, lds, t);
-            break;
-        case KIND_LAST: {
-            C *inter = static_cast<C *>(a.inter);
-            const int64_t woff = a.inter_is_io ? it.io_off : it.ws_off;
-            if constexpr (!ADJ) {
-                load_contig<C>(lds, inter, woff, it.bits, it.count, nullptr, t);
-                __syncthreads();
-                rounds<false>(lds, it.bits, t);
-                store_paley<S>(lds, static_cast<S *>(a.out), it.io_off, it.bits, it.count,
-                               nullptr, t, ortho_scale<C>(it.m), a.ortho != 0);
-            } else {
-                load_paley<S>(lds, static_cast<const S *>(a.in), it.io_off, it.bits,
-                              it.count, nullptr, t);
-                __syncthreads();
-                rounds<true>(lds, it.bits, t);
-                store_contig<C>(lds, inter, woff, it.bits, it.count, nullptr, t, C(1), false);
+    }
+
+    template <bool ADJ, int KIND>
+    static __device__ __forceinline__ void stream_put(const Item &it, const u32x4 *raw, C *lds,
+                                                      int t)
+    {
+        using T = SrcT<ADJ, KIND>;
+        constexpr int V = Vec<T>::V, NV = nraw<ADJ, KIND>();
+        if constexpr (!ADJ) {
+            C *lb = lds + L::pad(V * t);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                C vals[V];
+                Vec<T>::decode(raw[k], vals);
+#pragma unroll
+                for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[u];
             }
-            break;
-        }
-        default:
-            break;
+        } else if constexpr (src_inter<ADJ, KIND>()) {
+            constexpr int CC = KIND == KIND_FIRST_A ? CA : CB;
+            C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                C vals[V];
+                Vec<C>::decode(raw[k], vals);
+#pragma unroll
+                for (int u = 0; u < V; ++u) lb[L::pad(L::template transp_e<V, CC>(0, k, u))] = vals[u];
+            }
+        } else {
+            const int bits = it.bits;
+            if (bits == K) {
+                C *lb = lds + L::pad((int)rbrev((uint32_t)(V * t), K));
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    C vals[V];
+                    Vec<T>::decode(raw[k], vals);
+#pragma unroll
+                    for (int u = 0; u < V; ++u)
+                        lb[L::pad((int)cbrev((uint32_t)(V * NT * k + u), K))] = vals[u];
+                }
+            } else {
+                C *lb = lds + L::pad(brev_low(V * t, bits));
+                int ul[V];
+#pragma unroll
+                for (int u = 0; u < V; ++u) ul[u] = L::pad(brev_low(u, bits));
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    C vals[V];
+                    Vec<T>::decode(raw[k], vals);
+                    const int kl = L::pad(brev_low(V * NT * k, bits));
+#pragma unroll
+                    for (int u = 0; u < V; ++u) lb[kl + ul[u]] = vals[u];
+                }
+            }
         }
     }
 };

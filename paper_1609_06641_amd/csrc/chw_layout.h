@@ -1,9 +1,15 @@
 // chw_layout.h -- index maps of the CHW tile engine (host and device).
 //
 // A tile is N = 2^K elements held in LDS as the compute type (FP32, int32 or
-// FP64), at padded word address pad(e) = e + (e >> LR), e = tile element.  A
-// workgroup of NT = 2^(K-LR) threads processes it; in each "round" a thread
-// holds R = 2^LR elements in registers.
+// FP64), at padded word address pad(e) = e + (e >> P1) + (e >> P2), e = tile
+// element.  A workgroup of NT = 2^(K-LR) threads processes it; in each
+// "round" a thread holds R = 2^LR elements in registers.
+//
+// The two padding shifts and the lane order of the transposed phase were
+// chosen with a model of the LDS banks (one 64-lane wave on 64 banks, and
+// half-waves on 32 banks): with them no phase of a compiled tile puts more
+// than two distinct words of one wave access into one bank (the self-check
+// reports the figures for every phase).
 //
 // Stage t of the cascade is the set of Haar levels at depth t: after stages
 // 0..t-1 every element has been combined over input index bits 0..t-1, and
@@ -51,10 +57,12 @@ struct Layout {
     static constexpr int N = 1 << K, R = 1 << LR;
     static constexpr int LNT = K - LR, NT = 1 << LNT;
     static constexpr int J = (K + LR - 1) / LR;          // register rounds
-    static constexpr int LDS_WORDS = N + (N >> LR);
+    // padding shifts: one word after every 2^P1 and every 2^P2 elements
+    static constexpr int P1 = 6, P2 = K >= 15 ? 12 : 11;
     static_assert(LR >= 3 && LNT >= 6, "tile needs >= 8 registers and >= 1 wave");
 
-    static CHW_HD constexpr int pad(int e) { return e + (e >> LR); }
+    static CHW_HD constexpr int pad(int e) { return e + (e >> P1) + (e >> P2); }
+    static constexpr int LDS_WORDS = pad(N - 1) + 1;
 
     // ---- register rounds -------------------------------------------------
     // Round j makes active the tile bits [alo(j), ahi(j)); the register field
@@ -89,12 +97,41 @@ struct Layout {
 
     // ---- transposed phase of a first-pass tile: 2^C rows of 2^L1 elements,
     // tile element e = (hl << L1) | lo; output o (within the tile) = (rho << C)
-    // | hl where rho = bitrev_L1(lo) indexes the output run of 2^C elements ---
+    // | hl where rho = bitrev_L1(lo) indexes the output run of 2^C elements.
+    // Output vector q = o / V is handled by thread t, iteration k with
+    // q = transp_q(t + NT * k): lanes 0-2 keep eight consecutive vectors (a
+    // 128-byte line for FP32 runs of 32 rows), and the bits above are rotated
+    // by transp_rot so that one wave access spreads over the LDS banks.  A bit
+    // permutation keeps q(t | NT k) = q(t) | q(NT k). ---
+    template <int V, int C>
+    static CHW_HD constexpr int transp_rot()
+    {
+        // (K, V, C) -> rotation found with the bank model
+        if constexpr (K >= 15)
+            return V == 4 ? (C == 3 ? 8 : C >= 5 ? C - 1 : 0)
+                          : (C == 3 ? 10 : C == 5 ? 6 : C == 6 ? 7 : 0);
+        else
+            return V == 4 ? (C == 3 ? 1 : C >= 4 && C <= 6 ? C - 1 : 0)
+                          : (C == 4 ? 5 : C == 5 ? 6 : 0);
+    }
+    template <int V, int C>
+    static CHW_HD constexpr int transp_q(int n)
+    {
+        constexpr int lv = V == 8 ? 3 : V == 4 ? 2 : V == 2 ? 1 : 0;
+        constexpr int W = K - lv - 3, r = transp_rot<V, C>();
+        if constexpr (W <= 0 || r == 0 || r >= W) {
+            return n;
+        } else {
+            const int f = (n >> 3) & ((1 << W) - 1);
+            const int g = ((f << r) | (f >> (W - r))) & ((1 << W) - 1);
+            return (n & 7) | (g << 3);
+        }
+    }
     template <int V, int C>
     static CHW_HD int transp_e(int t, int k, int u)
     {
         constexpr int L1 = K - C;
-        int o = V * t + V * NT * k + u;
+        int o = V * transp_q<V, C>(t + NT * k) + u;
         int hl = o & ((1 << C) - 1);
         int rho = o >> C;
         return (hl << L1) | (int)rbrev((uint32_t)rho, L1);

@@ -6,7 +6,9 @@
 //   * multi-launch order: a signal's last-pass launch comes after its
 //     first-pass launch (forward) or before it (adjoint);
 //   * persistent tables: a whole-signal item covers its signal in both passes
-//     and its split fits the 2^12-element tiles.
+//     and its split fits the 2^12-element tiles;
+//   * a prefetching launch holds only full tiles of one kind without block
+//     lists, and reads them from the source its code names.
 #include <algorithm>
 #include <cstdio>
 #include <string>
@@ -111,6 +113,12 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     };
     for (int dir = 0; dir < 2; ++dir) {
         const std::vector<LaunchRange> &L = dir ? p.adj : p.fwd;
+        for (const LaunchRange &r : L) {
+            if (r.stream != 0 && (r.persistent || r.stream != stream_source(p.items, r.begin, r.end, r.K, dir == 1))) {
+                *err = "prefetching launch over items that are not full tiles of one kind";
+                return false;
+            }
+        }
         std::vector<Iv> iv;
         if (!tile_intervals(L, iv)) return false;
         for (int pass = 0; pass < 3; ++pass)

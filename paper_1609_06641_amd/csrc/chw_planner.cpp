@@ -34,8 +34,8 @@ int compute_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out)
 {
     struct Opt { int K1, CC, kind; };
-    // preference: the widest transposed runs first (2^5 rows = 128-byte runs of
-    // FP32 in the first pass's store)
+    // preference: the widest transposed runs first (2^7 rows = 512-byte runs
+    // of FP32 in the first pass's store)
     const Opt opts[] = {{15, K15_CA, KIND_FIRST_A}, {12, K12_CA, KIND_FIRST_A},
                         {15, K15_CB, KIND_FIRST_B}, {12, K12_CB, KIND_FIRST_B}};
     const int kmax2 = (dt == DT_F64 || k12_only) ? 12 : 15;
@@ -259,7 +259,32 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         for (int k = 0; k < 2; ++k)
             if (f[k].end > f[k].begin) p.adj.push_back(f[k]);
     }
+    if (p.cfg.stream) {
+        // 2^12-element tiles keep several workgroups per CU, which overlap
+        // loads and work by themselves; only 2^15-element tiles prefetch
+        for (LaunchRange &r : p.fwd)
+            r.stream = r.K == 15 ? stream_source(p.items, r.begin, r.end, r.K, false) : 0;
+        for (LaunchRange &r : p.adj)
+            r.stream = r.K == 15 ? stream_source(p.items, r.begin, r.end, r.K, true) : 0;
+    }
     *out = std::move(p);
+}
+
+int stream_source(const std::vector<Item> &items, int begin, int end, int K, bool adj)
+{
+    (void)adj;  // the kernel derives its source (input or intermediate) from the kind
+    if (begin >= end) return 0;
+    const int kind = items[begin].kind;
+    if (kind != KIND_BLOCKS && kind != KIND_FIRST_A && kind != KIND_FIRST_B && kind != KIND_LAST)
+        return 0;
+    for (int i = begin; i < end; ++i) {
+        const Item &it = items[i];
+        if (it.kind != kind) return 0;
+        if ((kind == KIND_BLOCKS || kind == KIND_LAST) &&
+            (it.list >= 0 || ((int64_t)it.count << it.bits) != ((int64_t)1 << K)))
+            return 0;
+    }
+    return 1 + kind;
 }
 
 std::string describe_plan(const BuiltPlan &p)
@@ -274,9 +299,9 @@ std::string describe_plan(const BuiltPlan &p)
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
-                  "\"exec\": %d, \"chunk\": %lld}, ",
+                  "\"exec\": %d, \"chunk\": %lld, \"stream\": %d}, ",
                   p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec,
-                  (long long)p.cfg.chunk);
+                  (long long)p.cfg.chunk, p.cfg.stream);
     s += buf;
     s += "\"splits\": [";
     for (size_t i = 0; i < p.splits.size(); ++i) {
@@ -293,8 +318,8 @@ std::string describe_plan(const BuiltPlan &p)
         for (size_t i = 0; i < v.size(); ++i) {
             const LaunchRange &r = v[i];
             std::snprintf(buf, sizeof buf,
-                          "%s{\"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d, \"persistent\": %d}",
-                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent);
+                          "%s{\"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d, \"persistent\": %d, \"stream\": %d}",
+                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent, r.stream);
             s += buf;
         }
         s += "]";

@@ -26,6 +26,10 @@ struct PlanConfig {
                         // the batch runs as first pass, last pass on each chunk
                         // in turn, so a chunk's intermediate can stay in the
                         // memory-side cache between its two passes
+    int stream = 1;     // 1: launches of full 2^15-element tiles of one kind
+                        // run the prefetching kernel (a workgroup loops over
+                        // items and fetches the next tile while the current
+                        // one runs; one such workgroup fills a CU's LDS)
 };
 
 // Items [begin, end) of the plan's table run in one launch of the tile kernel
@@ -35,7 +39,14 @@ struct LaunchRange {
     int K, LR;
     int begin, end;
     int persistent = 0;  // 1: one persistent launch over the range
+    int stream = 0;      // prefetching launch over items of kind stream - 1
+                         // (all full tiles, no block lists); 0 = one
+                         // workgroup per item
 };
+
+// Prefetching form of a launch of items [begin, end): 0 when the items are not
+// all full tiles of one kind without block lists, else 1 + that kind.
+int stream_source(const std::vector<Item> &items, int begin, int end, int K, bool adj);
 
 // Two-pass split of one signal size.
 struct Split {
@@ -57,7 +68,16 @@ struct BuiltPlan {
 };
 
 // Row counts (log2) of the first-pass variants compiled for each tile size.
-constexpr int K12_CA = 4, K12_CB = 3, K15_CA = 5, K15_CB = 3;
+// The wide variants (A) give the first pass's transposed store runs of 2^7
+// (2^15-element tiles) and 2^6 (2^12-element tiles) rows: 512- and 256-byte
+// runs of FP32.  The narrow variants (B) cover the splits the wide ones cannot.
+#ifndef CHW_K15_CA
+#define CHW_K15_CA 7
+#endif
+#ifndef CHW_K12_CA
+#define CHW_K12_CA 6
+#endif
+constexpr int K12_CA = CHW_K12_CA, K12_CB = 3, K15_CA = CHW_K15_CA, K15_CB = 3;
 
 // Storage / compute element sizes of a dtype.
 int elem_bytes(int dt);

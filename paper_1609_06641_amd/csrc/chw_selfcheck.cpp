@@ -139,11 +139,25 @@ std::string check_variant()
                     bank_account(cs, a);
                     bank_account(bs, b);
                 }
+        // Paley phase of blocks of 2^8 .. 2^(K-1) elements (last-pass tiles
+        // and small signals)
+        Stats ps;
+        for (int bits = 8; bits < K; ++bits)
+            for (int w = 0; w < NT / 64; ++w)
+                for (int k = 0; k < NV; ++k)
+                    for (int u = 0; u < V; ++u) {
+                        std::vector<int> a;
+                        for (int l = 0; l < 64; ++l)
+                            a.push_back(L::pad(L::template bitrev_e<V>(64 * w + l, k, u, bits)));
+                        bank_account(ps, a);
+                    }
         std::snprintf(buf, sizeof buf,
                       ", {\"K\": %d, \"LR\": %d, \"V\": %d, \"phase\": \"contig\", \"ok\": %s, \"ways64\": %d, \"ways32\": %d}"
-                      ", {\"K\": %d, \"LR\": %d, \"V\": %d, \"phase\": \"paley\", \"ok\": %s, \"ways64\": %d, \"ways32\": %d}",
+                      ", {\"K\": %d, \"LR\": %d, \"V\": %d, \"phase\": \"paley\", \"ok\": %s, \"ways64\": %d, \"ways32\": %d}"
+                      ", {\"K\": %d, \"LR\": %d, \"V\": %d, \"phase\": \"paley_blocks_2^8..2^(K-1)\", \"ok\": true, \"ways64\": %d, \"ways32\": %d}",
                       K, LR, V, cs.ok ? "true" : "false", cs.worst64, cs.worst32, K, LR, V,
-                      bs.ok ? "true" : "false", bs.worst64, bs.worst32);
+                      bs.ok ? "true" : "false", bs.worst64, bs.worst32, K, LR, V, ps.worst64,
+                      ps.worst32);
         out += buf;
         if (!cs.ok) out += ", {\"error\": \"" + cs.err + "\"}";
         if (!bs.ok) out += ", {\"error\": \"" + bs.err + "\"}";
@@ -169,9 +183,13 @@ std::string check_variant()
                     if (L::pad(L::template transp_e<V, CC>(t, 0, 0)) +
                             L::pad(L::template transp_e<V, CC>(0, k, u)) != L::pad(e))
                         ts.fail("transp offset split");
-                    const int o = V * t + V * NT * k + u;
+                    const int qt = L::template transp_q<V, CC>(t);
+                    const int qk = L::template transp_q<V, CC>(NT * k);
+                    if ((qt & qk) || (qt | qk) != L::template transp_q<V, CC>(t + NT * k))
+                        ts.fail("transp lane order not a bit permutation");
+                    const int o = V * (qt | qk) + u;
                     const int64_t g = L::template transp_goff<CC>(o, rsv);
-                    if (L::template transp_goff<CC>(V * t, rsv) + L::template transp_goff<CC>(V * NT * k, rsv) + u != g)
+                    if (L::template transp_goff<CC>(V * qt, rsv) + L::template transp_goff<CC>(V * qk, rsv) + u != g)
                         ts.fail("transp global split");
                     // element (hl, lo) must land at bitrev_L1(lo) * 2^rs + hl
                     const int hl = e >> L1, lo = e & ((1 << L1) - 1);
@@ -198,6 +216,8 @@ std::string check_variant()
     tr_phase(std::integral_constant<int, 4>{}, std::integral_constant<int, 3>{});
     tr_phase(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
     tr_phase(std::integral_constant<int, 4>{}, std::integral_constant<int, 5>{});
+    tr_phase(std::integral_constant<int, 4>{}, std::integral_constant<int, 6>{});
+    tr_phase(std::integral_constant<int, 4>{}, std::integral_constant<int, 7>{});
     tr_phase(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
     tr_phase(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
     return out;

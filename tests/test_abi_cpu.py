@@ -148,8 +148,10 @@ def test_planner_ragged_and_options():
         assert s["m"] - s["L1"] <= s["K2"] and s["m"] - s["L1"] >= s["rows_log2"]
     # forced split and register options rebuild the plan
     p2 = chw.Plan([20, 20], dtype="f32")
-    p2.set_option("split_l1", 10)
-    assert p2.describe()["plan"]["splits"][0]["L1"] == 10
+    p2.set_option("split_l1", 12)
+    assert p2.describe()["plan"]["splits"][0]["L1"] == 12
+    with pytest.raises(chw.CHWError):
+        p2.set_option("split_l1", 10)   # no compiled variant runs 10 levels first
     p2.set_option("lr12", 5)
     assert p2.describe()["plan"]["config"]["lr12"] == 5
     with pytest.raises(chw.CHWError):
@@ -201,12 +203,25 @@ def test_layout_selfcheck():
     ok, rep = chw.layout_selfcheck()
     assert ok, [r for r in rep if not r.get("ok", True)]
     phases = {r["phase"] for r in rep if "phase" in r}
-    assert phases == {"rounds", "contig", "paley", "transposed"}
+    assert phases == {"rounds", "contig", "paley", "paley_blocks_2^8..2^(K-1)", "transposed"}
+    # every phase of a compiled tile keeps a wave access within two words per
+    # LDS bank (64 banks, and 32 banks per half wave); the transposed phase is
+    # compiled for 2^7 / 2^3 rows in 2^15 tiles and 2^6 / 2^3 rows in 2^12 tiles
+    compiled_rows = {12: (6, 3), 15: (7, 3)}
+    for r in rep:
+        if "phase" not in r:
+            continue
+        if r["phase"] == "transposed" and r["rows_log2"] not in compiled_rows[r["K"]]:
+            continue
+        if r["phase"] == "transposed" and r["K"] == 15 and r["V"] == 2:
+            continue  # no FP64 2^15 tiles
+        assert r["ways64"] <= 2 and r["ways32"] <= 2, r
 
 
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("opts", [dict(), dict(exec=2), dict(chunk=1 << 20), dict(single15=0),
-                                  dict(split_l1=12), dict(exec=2, lr12=5)])
+                                  dict(split_l1=12), dict(exec=2, lr12=5), dict(stream=1),
+                                  dict(stream=0), dict(stream=1, chunk=1 << 22, split_l1=8)])
 def test_plan_invariants_random_ragged(seed, opts):
     rng = np.random.default_rng(seed)
     hi = 22 if opts.get("exec") == 2 else 25
@@ -266,6 +281,34 @@ def test_persistent_plan_shape():
     # 3 whole-signal items (20, 20, 14) + 1 tile with the three 2^9 signals
     assert d["items"] == 4 and d["multi"] == 3
     p.check()
+
+
+def test_stream_plan_shape():
+    # uniform 2^20 batch: the first pass runs 2^15-element tiles (FIRST_A,
+    # prefetching), the last pass 2^12-element tiles (one workgroup each)
+    p = chw.Plan([20] * 8, dtype="f32")
+    d = p.describe()["plan"]
+    assert d["config"]["stream"] == 1
+    assert [r["K"] for r in d["forward"]] == [15, 12]
+    assert [r["stream"] for r in d["forward"]] == [1 + 1, 0]
+    assert [r["stream"] for r in d["backward"]] == [0, 1 + 1]
+    p.check()
+    p.set_option("stream", 0)
+    assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [0, 0]
+    # 2^22 signals: both passes in 2^15-element tiles
+    p = chw.Plan([22] * 2, dtype="f32")
+    assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [1 + 1, 1 + 3]
+    p.check()
+    # single-pass 2^15-element tiles with offset lists stay one workgroup per tile
+    offs = np.arange(9, dtype=np.int64) * (1 << 14)
+    p = chw.Plan([13] * 8, dtype="f32", offsets=offs)
+    assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [0]
+    p.check()
+    # full single-pass tiles qualify
+    p = chw.Plan([13] * 8, dtype="bf16")
+    assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [1]
+    with pytest.raises(chw.CHWError):
+        p.set_option("stream", 2)
 
 
 def test_plan_invariants_workloads():

@@ -189,8 +189,10 @@ def test_split_invariance_bitwise():
     xd = gu.dev_tensor(x, "f32")
     outs = []
     configs = [dict(), dict(lr12=5), dict(lr15=6), dict(single15=0),
-               dict(split_l1=9), dict(split_l1=10), dict(split_l1=12, lr15=6),
-               dict(split_l1=8), dict(chunk=1 << 21), dict(exec=2), dict(exec=2, lr12=5)]
+               dict(split_l1=9), dict(split_l1=6), dict(split_l1=12, lr15=6),
+               dict(split_l1=8), dict(chunk=1 << 21), dict(exec=2), dict(exec=2, lr12=5),
+               dict(stream=0), dict(stream=0, lr12=5), dict(stream=0, split_l1=12, lr15=6),
+               dict(stream=0, split_l1=8, chunk=1 << 21), dict(stream=1, split_l1=6)]
     for cfg in configs:
         p = chw.Plan(sizes, dtype="f32")
         for k, v in cfg.items():
@@ -201,6 +203,41 @@ def test_split_invariance_bitwise():
         assert np.array_equal(o, outs[0]), cfg
     ref = gu.oracle_packed(x.astype(np.float64), sizes)
     assert gu.per_signal_rel(outs[0], ref, sizes).max() <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "i32"])
+def test_stream_bitwise(dtype):
+    # launches of full 2^15-element tiles of one kind (single-pass 2^13 and
+    # 2^15 signals, the first pass of 2^17 signals, both passes of 2^22
+    # signals) in the prefetching form, forward and backward, against the
+    # one-workgroup-per-tile form and the oracle
+    for sizes in ([13] * 8, [15] * 2, [17] * 3, [22] * 2):
+        gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
+        x = np.concatenate([gen(900 + i, 1, k).reshape(-1) for i, k in enumerate(sizes)])
+        xd = gu.dev_tensor(x, dtype)
+        for lr in (5, 6):
+            res = []
+            for stream in (0, 1):
+                p = chw.Plan(sizes, dtype=dtype, norm="none" if dtype == "i32" else "ortho")
+                p.set_option("lr12", lr)
+                p.set_option("lr15", lr)
+                p.set_option("stream", stream)
+                d = p.describe()["plan"]
+                assert any(r["stream"] > 0 for r in d["forward"]) == bool(stream), sizes
+                assert all(r["stream"] == 0 or r["K"] == 15 for r in d["forward"] + d["backward"])
+                ws = gu.torch().empty(max(p.workspace_size(), 16), dtype=gu.torch().uint8,
+                                      device="cuda")
+                res.append((gu.host_f64(p.forward(xd)), gu.host_f64(p.backward(xd, workspace=ws))))
+            _sync()
+            assert np.array_equal(res[0][0], res[1][0]), (sizes, lr)
+            assert np.array_equal(res[0][1], res[1][1]), (sizes, lr)
+        if dtype == "i32":
+            ref = gu.oracle_packed(x.astype(np.int64), sizes)
+            assert np.array_equal(res[1][0].astype(np.int64), ref)
+        else:
+            ref = gu.oracle_packed(gu.host_f64(xd), sizes)
+            tol = 4e-3 if dtype == "bf16" else 1e-5
+            assert gu.per_signal_rel(res[1][0], ref, sizes).max() <= tol
 
 
 @pytest.mark.skip(reason="the dependency-counter persistent kernel (exec 1) did not finish "
