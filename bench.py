@@ -130,7 +130,7 @@ def launch_names(plan, direction="forward"):
     names = []
     if d["tiny"]:
         names.append("chw_tiny_kernel")
-    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST"}
+    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST", 5: "FIRST_C"}
     for r in d[direction]:
         if r["persistent"]:
             kind = "chw_persistent_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])

@@ -273,7 +273,7 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         };
         if (r.persistent) {
             e = v->launch_persistent(dim3(std::min(a.nitems, grid_cap(v->fn_persistent))), stream, a);
-        } else if (r.stream >= 1 && r.stream <= 4) {
+        } else if (r.stream >= 1 && r.stream <= 5) {
             const void *fn = v->fn_stream[r.stream - 1];
             e = v->launch_stream[r.stream - 1](dim3(std::min(a.nitems, grid_cap(fn))), stream, a);
         } else {
@@ -607,7 +607,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
     }
     std::vector<int> l1s = {-1};
     if (has_multi)
-        for (int l1 : {15 - K15_CA, 12 - K12_CA, 15 - K15_CB, 12 - K12_CB}) {
+        for (int l1 : {15 - K15_CA, 12 - K12_CA, 15 - K15_CM, 12 - K12_CM, 15 - K15_CB, 12 - K12_CB}) {
             Split sp;
             bool ok = true;
             for (int32_t m : plan->m)

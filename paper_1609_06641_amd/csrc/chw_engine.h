@@ -203,7 +203,11 @@ struct Engine {
     using C = typename Types<DT>::C;
     static constexpr int N = L::N, NT = L::NT, R = L::R, J = L::J;
     static constexpr bool NT_IN = CHW_NT_IN, NT_OUT = CHW_NT_OUT, NT_INTER = CHW_NT_INTER;
+    static constexpr int CM = mid_rows(K);
     static_assert(CA >= 2 && CB >= 2 && CA < K && CB < K, "first-pass row counts");
+    // row count (log2) of a first-pass kind
+    template <int KIND>
+    static constexpr int rows_of() { return KIND == KIND_FIRST_A ? CA : KIND == KIND_FIRST_B ? CB : CM; }
 
     // ---- butterflies -------------------------------------------------------
     // One stage on register bit rb: v[i] (bit clear) and v[i | 1 << rb]
@@ -500,6 +504,10 @@ struct Engine {
             if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
             else load_transp<CB>(lds, inter, first_base<CB>(it, a), it.h0, it.rs, t);
             break;
+        case KIND_FIRST_C:
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
+            else load_transp<CM>(lds, inter, first_base<CM>(it, a), it.h0, it.rs, t);
+            break;
         case KIND_LAST:
             if constexpr (!ADJ) load_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t);
             else load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, nullptr, t);
@@ -523,8 +531,8 @@ struct Engine {
             rounds<ADJ>(lds, it.bits, t);
             if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
-        } else if constexpr (KIND == KIND_FIRST_A || KIND == KIND_FIRST_B) {
-            constexpr int CC = KIND == KIND_FIRST_A ? CA : CB;
+        } else if constexpr (is_first_kind(KIND)) {
+            constexpr int CC = rows_of<KIND>();
             rounds<ADJ>(lds, K - CC, t);
             if constexpr (!ADJ) store_transp<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho);
@@ -543,6 +551,7 @@ struct Engine {
         case KIND_BLOCKS: finish_kind<ADJ, KIND_BLOCKS>(it, a, lds, t); break;
         case KIND_FIRST_A: finish_kind<ADJ, KIND_FIRST_A>(it, a, lds, t); break;
         case KIND_FIRST_B: finish_kind<ADJ, KIND_FIRST_B>(it, a, lds, t); break;
+        case KIND_FIRST_C: finish_kind<ADJ, KIND_FIRST_C>(it, a, lds, t); break;
         case KIND_LAST: finish_kind<ADJ, KIND_LAST>(it, a, lds, t); break;
         default: break;
         }
@@ -571,7 +580,7 @@ struct Engine {
     template <bool ADJ, int KIND>
     static constexpr bool src_inter()
     {
-        return ADJ ? (KIND == KIND_FIRST_A || KIND == KIND_FIRST_B) : KIND == KIND_LAST;
+        return ADJ ? is_first_kind(KIND) : KIND == KIND_LAST;
     }
     template <bool ADJ, int KIND>
     using SrcT = typename std::conditional<src_inter<ADJ, KIND>(), C, S>::type;
@@ -585,7 +594,7 @@ struct Engine {
         using T = SrcT<ADJ, KIND>;
         constexpr int V = Vec<T>::V, NV = nraw<ADJ, KIND>();
         if constexpr (ADJ && src_inter<ADJ, KIND>()) {
-            constexpr int CC = KIND == KIND_FIRST_A ? CA : CB;
+            constexpr int CC = rows_of<KIND>();
             const C *base = static_cast<const C *>(a.inter) + first_base<CC>(it, a) + it.h0;
             const uint32_t toff =
                 (uint32_t)L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), it.rs);
@@ -620,7 +629,7 @@ struct Engine {
                 for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[u];
             }
         } else if constexpr (src_inter<ADJ, KIND>()) {
-            constexpr int CC = KIND == KIND_FIRST_A ? CA : CB;
+            constexpr int CC = rows_of<KIND>();
             C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
 #pragma unroll
             for (int k = 0; k < NV; ++k) {

@@ -90,7 +90,7 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
                     const int64_t n = (int64_t)1 << it.m;
                     iv.push_back({it.io_off, it.io_off + n, 1, (int)li});
                     iv.push_back({it.io_off, it.io_off + n, 2, (int)li});
-                } else if (it.kind == KIND_FIRST_A || it.kind == KIND_FIRST_B) {
+                } else if (is_first_kind(it.kind)) {
                     iv.push_back({it.io_off, it.io_off + ((int64_t)1 << K), 1, (int)li});
                 } else if (it.kind == KIND_LAST) {
                     iv.push_back({it.io_off, it.io_off + ((int64_t)it.count << it.bits), 2, (int)li});

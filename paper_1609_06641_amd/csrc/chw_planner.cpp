@@ -37,10 +37,12 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out)
     // preference: the widest transposed runs first (2^7 rows = 512-byte runs
     // of FP32 in the first pass's store)
     const Opt opts[] = {{15, K15_CA, KIND_FIRST_A}, {12, K12_CA, KIND_FIRST_A},
+                        {15, K15_CM, KIND_FIRST_C}, {12, K12_CM, KIND_FIRST_C},
                         {15, K15_CB, KIND_FIRST_B}, {12, K12_CB, KIND_FIRST_B}};
     const int kmax2 = (dt == DT_F64 || k12_only) ? 12 : 15;
     for (const Opt &o : opts) {
         if (o.K1 == 15 && (dt == DT_F64 || k12_only)) continue;
+        if (o.kind == KIND_FIRST_C && k12_only) continue;  // whole-signal items: A or B
         const int L1 = o.K1 - o.CC;
         if (forced_l1 > 0 && L1 != forced_l1) continue;
         const int b = m - L1;                 // levels left for the second pass
@@ -275,8 +277,7 @@ int stream_source(const std::vector<Item> &items, int begin, int end, int K, boo
     (void)adj;  // the kernel derives its source (input or intermediate) from the kind
     if (begin >= end) return 0;
     const int kind = items[begin].kind;
-    if (kind != KIND_BLOCKS && kind != KIND_FIRST_A && kind != KIND_FIRST_B && kind != KIND_LAST)
-        return 0;
+    if (kind != KIND_BLOCKS && !is_first_kind(kind) && kind != KIND_LAST) return 0;
     for (int i = begin; i < end; ++i) {
         const Item &it = items[i];
         if (it.kind != kind) return 0;

@@ -21,12 +21,25 @@ enum ItemKind : int32_t {
     // Last HBM pass: blocks of 2^bits contiguous intermediate elements (the
     // remaining CHW_{m-L1} on each block), Paley-ordered store.
     KIND_LAST = 3,
+    // First HBM pass with the middle row count 2^CM (K15_CM / K12_CM below).
+    KIND_FIRST_C = 4,
     // Persistent launch: a whole multi-pass signal (first-pass tiles with the
     // variant-A / variant-B row count, then its last-pass tiles) run by one
     // workgroup.
-    KIND_SIGNAL_A = 4,
-    KIND_SIGNAL_B = 5,
+    KIND_SIGNAL_A = 5,
+    KIND_SIGNAL_B = 6,
 };
+
+constexpr bool is_first_kind(int kind)
+{
+    return kind == KIND_FIRST_A || kind == KIND_FIRST_B || kind == KIND_FIRST_C;
+}
+
+// Middle row count (log2) of the first-pass tiles: 2^5 rows in 2^15-element
+// tiles, 2^4 rows in 2^12-element tiles (128- and 64-byte FP32 runs), for the
+// splits the wide variant cannot take.
+constexpr int K15_CM = 5, K12_CM = 4;
+constexpr int mid_rows(int K) { return K >= 15 ? K15_CM : K12_CM; }
 
 // 64-byte work item.  Offsets are element offsets:
 //   io_off : start of the tile's contiguous chunk in x / g / y space

@@ -22,8 +22,8 @@ struct ItemsVariant {
     const void *fn;         // kernel symbol (occupancy queries)
     ItemsLauncher launch_persistent;  // persistent form (K = 12 only), or null
     const void *fn_persistent;
-    ItemsLauncher launch_stream[4];   // prefetching form for items of kind
-    const void *fn_stream[4];         // BLOCKS, FIRST_A, FIRST_B, LAST
+    ItemsLauncher launch_stream[5];   // prefetching form for items of kind
+    const void *fn_stream[5];         // BLOCKS, FIRST_A, FIRST_B, LAST, FIRST_C
 };
 
 struct TinyVariant {

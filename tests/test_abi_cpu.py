@@ -151,7 +151,7 @@ def test_planner_ragged_and_options():
     p2.set_option("split_l1", 12)
     assert p2.describe()["plan"]["splits"][0]["L1"] == 12
     with pytest.raises(chw.CHWError):
-        p2.set_option("split_l1", 10)   # no compiled variant runs 10 levels first
+        p2.set_option("split_l1", 11)   # no compiled variant runs 11 levels first
     p2.set_option("lr12", 5)
     assert p2.describe()["plan"]["config"]["lr12"] == 5
     with pytest.raises(chw.CHWError):
@@ -206,8 +206,9 @@ def test_layout_selfcheck():
     assert phases == {"rounds", "contig", "paley", "paley_blocks_2^8..2^(K-1)", "transposed"}
     # every phase of a compiled tile keeps a wave access within two words per
     # LDS bank (64 banks, and 32 banks per half wave); the transposed phase is
-    # compiled for 2^7 / 2^3 rows in 2^15 tiles and 2^6 / 2^3 rows in 2^12 tiles
-    compiled_rows = {12: (6, 3), 15: (7, 3)}
+    # compiled for 2^7 / 2^5 / 2^3 rows in 2^15 tiles and 2^6 / 2^4 / 2^3 rows in
+    # 2^12 tiles
+    compiled_rows = {12: (6, 4, 3), 15: (7, 5, 3)}
     for r in rep:
         if "phase" not in r:
             continue
