@@ -285,15 +285,53 @@ def run_other(args, dev, stream):
     y = torch.empty_like(x)
     ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device=dev)
     configure(plan, args, x, y, ws)
-    fn = lambda: plan.forward(x, out=y, workspace=ws)  # noqa: E731
+    es = x.element_size()
+    k = args.signed_rounds
+    if k > 0:
+        # y = H D_k ... H D_1 x with one diagonal per round shared by the
+        # signals, fused into the tile kernels; the unfused form (torch sign
+        # flips, then the plain transform per round) is timed beside it
+        m = int(plan.log2_sizes.max())
+        diags = workloads.sign_rounds(w.seed + 1, k, 1 << m)
+        words = workloads.pack_sign_bits(diags).reshape(-1).view(np.int32)
+        signs = torch.from_numpy(words.copy()).to(dev)
+        dflat = [torch.from_numpy(workloads.expand_shared_signs(
+            diags[r:r + 1].astype(np.float32), plan.log2_sizes, plan.offsets)[0]).to(tdt).to(dev)
+            for r in range(k)]
+        fn = lambda: plan.forward_signed(x, signs, "shared", k, out=y, workspace=ws)  # noqa: E731
+
+        def unfused():
+            v = x
+            for r in range(k):
+                v = plan.forward(v * dflat[r], out=y, workspace=ws)
+        ms_unfused = time_steps(unfused, args.steps, args.warmup, stream)
+    else:
+        fn = lambda: plan.forward(x, out=y, workspace=ws)  # noqa: E731
     ms = time_steps(fn, args.steps, args.warmup, stream)
     launches = launch_breakdown(plan, fn, args.steps) if not args.no_launch_timing else [ms]
-    es = x.element_size()
+    # algorithmic bytes: one read and one write of the data, plus the sign bits
+    bpe = 2 * es + (k / 8.0 if k > 0 else 0.0)
+    names = launch_names(plan)
+    if k > 1:  # one set of launches per round
+        names = ["%s round %d" % (nm, r + 1) for r in range(k) for nm in names]
     out = {"workload": w.name, "ms_per_step": round(ms, 4),
            "Gelem_s": round(elems / (ms / 1e3) / 1e9, 2),
-           "roofline": roofline(elems, 2 * es, launches, launch_names(plan), None),
+           "roofline": roofline(elems, bpe, launches, names, None),
            "plan": plan.describe()["plan"]["config"],
            "forward_calls": args.warmup + args.steps * (1 if args.no_launch_timing else 2)}
+    if k > 0:
+        from oracle import metrics, signed
+        torch.cuda.synchronize()
+        idx = [0, w.batch - 1] if not w.name.startswith("ragged") else []
+        n = 1 << int(plan.log2_sizes[0])
+        xh = x.double().cpu().numpy()
+        yh = y.double().cpu().numpy()
+        rel = max([float(metrics.rel_l2(yh[i * n:(i + 1) * n],
+                                        signed.signed_forward(xh[i * n:(i + 1) * n], list(diags))))
+                   for i in idx] or [0.0])
+        out["signed"] = {"rounds": k, "diagonal": "shared by the signals",
+                         "unfused_ms_per_step": round(ms_unfused, 4),
+                         "parity": {"sampled_signals": idx, "max_rel_l2": rel}}
     if args.copy_gib > 0:
         out["copy_calibration"] = copy_calibration(args.copy_gib, dev, stream, args.steps)
     print(json.dumps(out), flush=True)
@@ -404,6 +442,8 @@ def main():
     ap.add_argument("--no-launch-timing", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--workload", default="plain_2p20_f32")
+    ap.add_argument("--signed-rounds", type=int, default=0,
+                    help="with --workload: time y = H D_k ... H D_1 x (k rounds, fused diagonals)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="also time a plain device copy of this many GiB (calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))

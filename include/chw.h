@@ -89,6 +89,19 @@ enum {
 #define CHW_MAX_LOG2 27
 /* Largest supported log2 signal size for CHW_F64. */
 #define CHW_MAX_LOG2_F64 20
+/* Largest number of rounds of a signed call (chw_forward_signed). */
+#define CHW_MAX_ROUNDS 64
+
+/* Layout of the random-sign diagonals of chw_forward_signed. */
+typedef enum {
+    CHW_SIGNS_PER_ELEMENT = 0,  /* bit e of a round's words is the sign of
+                                   element e of the buffers (e counts from
+                                   element 0, gaps included)                */
+    CHW_SIGNS_SHARED = 1        /* bit j is the sign of element j of every
+                                   signal (one diagonal shared by all
+                                   signals; a signal of 2^m elements uses
+                                   bits 0 .. 2^m - 1)                       */
+} chw_sign_mode;
 
 /*
  * chw_plan -- validate a batch description and build a plan.
@@ -146,6 +159,45 @@ chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
  * rules as chw_forward. */
 chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace,
                         void *stream);
+
+/*
+ * chw_forward_signed -- randomized Hadamard transform with the random-sign
+ * diagonals fused into the tile kernels (not part of the paper: the step
+ * that usually precedes the transform in sketching and Hadamard rotations):
+ *     y_i = H D_k ... H D_2 H D_1 x_i          (k = rounds, H = H_{m_i})
+ * where D_r = diag(d_r), d_r[j] = -1 where the sign bit is set, else +1.
+ * Round r's diagonal multiplies the vector the round reads: x for r = 1, the
+ * dyadic-ordered output of round r - 1 otherwise.  Each round is one complete
+ * transform (orthonormal or not as the plan says) whose output is stored in
+ * y in the plan's dtype; rounds after the first run in place on y.
+ *
+ *   signs   device array of rounds * W uint32 words, 4-byte aligned, W =
+ *           chw_sign_words(plan, mode); round r (0-based) uses words
+ *           [r W, (r + 1) W).  Bit b of the round is bit (b % 32) of word
+ *           b / 32; b is chosen by `mode`.  Read only.
+ *   mode    CHW_SIGNS_PER_ELEMENT or CHW_SIGNS_SHARED.
+ *   rounds  1 .. CHW_MAX_ROUNDS.  rounds > 1 with signals above 2^12
+ *           elements needs a workspace (the later rounds run in place).
+ * Other arguments and errors as chw_forward; signs = NULL or a misaligned
+ * signs pointer gives CHW_ERR_INVALID_ARGUMENT / CHW_ERR_MISALIGNED.  The
+ * sign flips are exact, so with d = +1 everywhere and rounds = 1 the result
+ * equals chw_forward bit for bit.
+ */
+chw_status chw_forward_signed(chw_plan_t plan, const void *x, void *y, void *workspace,
+                              const uint32_t *signs, chw_sign_mode mode, int rounds,
+                              void *stream);
+
+/* chw_backward_signed -- the adjoint of chw_forward_signed:
+ *     y_i = D_1 H^T D_2 H^T ... D_k H^T g_i
+ * (rounds in reverse order, each diagonal applied to its round's output as
+ * it is stored).  Same arguments and rules as chw_forward_signed. */
+chw_status chw_backward_signed(chw_plan_t plan, const void *g, void *y, void *workspace,
+                               const uint32_t *signs, chw_sign_mode mode, int rounds,
+                               void *stream);
+
+/* Words per round W of the sign arrays of this plan: ceil(2^{max m_i} / 32)
+ * for CHW_SIGNS_SHARED, ceil(offsets[batch] / 32) for CHW_SIGNS_PER_ELEMENT. */
+chw_status chw_sign_words(chw_plan_t plan, chw_sign_mode mode, size_t *words);
 
 /* Release a plan and its device tables and graphs.  NULL is a no-op.  The
  * caller must have synchronized every stream the plan was used on. */

@@ -23,6 +23,7 @@ FLAG_GRAPH = 1 << 0
 FLAG_NO_AUTOTUNE = 1 << 1
 FLAG_PERSISTENT = 1 << 2
 FLAG_MULTI_LAUNCH = 1 << 3
+SIGN_MODES = {"per_element": 0, "shared": 1}
 
 # symbols declared in include/chw.h: name -> (restype, argtypes)
 _VP = ctypes.c_void_p
@@ -40,6 +41,9 @@ SIGNATURES = {
     "chw_launch_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_int)]),
     "chw_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int]),
+    "chw_forward_signed": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
+    "chw_backward_signed": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
+    "chw_sign_words": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "chw_layout_selfcheck": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
     "chw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "chw_last_error": (ctypes.c_char_p, []),
@@ -190,7 +194,7 @@ class Plan:
             self._ws[key] = ws
         return ws
 
-    def _call(self, fn, x, out, workspace, stream, adjoint):
+    def _call(self, fn, x, out, workspace, stream, adjoint, signed=None):
         torch = _torch()
         self._tensor_check(x, "input")
         if out is None:
@@ -198,15 +202,52 @@ class Plan:
         self._tensor_check(out, "out")
         if workspace is None:
             narrow = self.dtype in ("bf16", "f16")
-            need = self.workspace_size() > 0 and (adjoint or narrow or
+            rounds = signed[2] if signed else 1
+            need = self.workspace_size() > 0 and (adjoint or narrow or rounds > 1 or
                                                   out.data_ptr() == x.data_ptr())
             workspace = self._workspace(x.device, need)
         ws_ptr = None if workspace is None else workspace.data_ptr()
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         sp = stream if isinstance(stream, int) else stream.cuda_stream
-        _check(fn(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()), _VP(ws_ptr), _VP(sp)))
+        if signed is None:
+            _check(fn(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()), _VP(ws_ptr), _VP(sp)))
+        else:
+            signs, mode, rounds = signed
+            _check(fn(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()), _VP(ws_ptr),
+                      _VP(signs.data_ptr()), SIGN_MODES[mode], int(rounds), _VP(sp)))
         return out
+
+    def sign_words(self, mode="shared"):
+        """uint32 words per round of a sign array in layout `mode`."""
+        n = ctypes.c_size_t()
+        _check(load().chw_sign_words(self.handle, SIGN_MODES[mode], ctypes.byref(n)))
+        return int(n.value)
+
+    def _sign_check(self, signs, mode, rounds):
+        torch = _torch()
+        if not isinstance(signs, torch.Tensor) or signs.dtype != torch.int32:
+            raise TypeError("signs must be an int32 tensor of packed sign bits")
+        if not signs.is_contiguous() or signs.device.type != "cuda":
+            raise ValueError("signs must be a contiguous GPU tensor")
+        need = int(rounds) * self.sign_words(mode)
+        if signs.numel() < need:
+            raise ValueError("signs holds %d words, %d rounds need %d" % (signs.numel(), rounds, need))
+
+    def forward_signed(self, x, signs, mode="shared", rounds=1, out=None, workspace=None,
+                       stream=None):
+        """out = H D_k ... H D_1 x per signal; signs: int32 tensor of packed bits
+        (rounds x sign_words(mode) words, bit set = sign flip)."""
+        self._sign_check(signs, mode, rounds)
+        return self._call(load().chw_forward_signed, x, out, workspace, stream, False,
+                          (signs, mode, rounds))
+
+    def backward_signed(self, g, signs, mode="shared", rounds=1, out=None, workspace=None,
+                        stream=None):
+        """out = D_1 H^T ... D_k H^T g per signal (adjoint of forward_signed)."""
+        self._sign_check(signs, mode, rounds)
+        return self._call(load().chw_backward_signed, g, out, workspace, stream, True,
+                          (signs, mode, rounds))
 
     def forward(self, x, out=None, workspace=None, stream=None):
         """out = H x for every signal (H'x in the unnormalized form)."""
@@ -273,3 +314,33 @@ def chw_function():
 def transform(x, plan):
     """Differentiable y = H x (applies CHWFunction)."""
     return chw_function().apply(x, plan)
+
+
+_sfn_cache = None
+
+
+def signed_function():
+    """torch.autograd.Function for y = H D_k ... H D_1 x (fused sign diagonals);
+    its backward applies the adjoint through chw_backward_signed."""
+    global _sfn_cache
+    if _sfn_cache is None:
+        torch = _torch()
+
+        class CHWSignedFunction(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, x, plan, signs, mode, rounds):
+                ctx.plan, ctx.signs, ctx.mode, ctx.rounds = plan, signs, mode, rounds
+                return plan.forward_signed(x.contiguous(), signs, mode, rounds)
+
+            @staticmethod
+            def backward(ctx, g):
+                gx = ctx.plan.backward_signed(g.contiguous(), ctx.signs, ctx.mode, ctx.rounds)
+                return gx, None, None, None, None
+
+        _sfn_cache = CHWSignedFunction
+    return _sfn_cache
+
+
+def signed_transform(x, plan, signs, mode="shared", rounds=1):
+    """Differentiable y = H D_k ... H D_1 x."""
+    return signed_function().apply(x, plan, signs, mode, rounds)

@@ -55,7 +55,19 @@ struct GraphEntry {
     const void *x;
     void *y;
     void *ws;
+    const uint32_t *signs;
+    int sign_shared;
+    int rounds;
     hipGraphExec_t exec;
+};
+
+// Random-sign diagonals of a call: `rounds` diagonals of `words` packed
+// words each (none when w is null).
+struct SignArgs {
+    const uint32_t *w = nullptr;
+    int shared = 0;
+    int rounds = 1;
+    size_t words = 0;
 };
 
 struct DeviceState {
@@ -221,15 +233,19 @@ chw_status mark(chw_plan_t p, DeviceState &ds, int i, hipStream_t stream)
     return CHW_OK;
 }
 
-// Enqueue the launches of one call on `stream`.
+// Enqueue the launches of one transform (one round) on `stream`; timing
+// events continue from the call's previous ones unless `fresh`.
 chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
-                   int inter_is_io, hipStream_t stream)
+                   int inter_is_io, hipStream_t stream, const uint32_t *signs = nullptr,
+                   int sign_shared = 0, bool fresh = true)
 {
     const BuiltPlan &b = p->built;
-    int nev = 0;
     chw_status ms;
-    ds.ev_used = 0;
-    if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
+    if (fresh) {
+        ds.ev_used = 0;
+        if ((ms = mark(p, ds, 0, stream)) != CHW_OK) return ms;
+    }
+    int nev = p->timing ? ds.ev_used : 0;
     LaunchArgs a{};
     a.in = x;
     a.out = y;
@@ -237,12 +253,14 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     a.inter_is_io = inter_is_io;
     a.list = ds.list;
     a.ortho = p->norm == CHW_ORTHONORMAL ? 1 : 0;
+    a.signs = signs;
+    a.sign_shared = sign_shared;
     if (!b.tiny_off.empty()) {
         const TinyVariant *tv = find_tiny_variant(p->dt, adj);
         if (!tv) return fail(CHW_ERR_UNSUPPORTED, "no tiny kernel for this dtype");
         const int n = (int)b.tiny_off.size();
         hipError_t e = tv->launch(dim3((n + 255) / 256), dim3(256), stream, x, y, ds.tiny_off,
-                                  ds.tiny_m, n, a.ortho);
+                                  ds.tiny_m, n, a.ortho, signs, sign_shared);
         if (e != hipSuccess) return hip_fail(e, "tiny kernel launch");
         if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
     }
@@ -285,13 +303,31 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     return CHW_OK;
 }
 
+// Every round of a call: the forward applies rounds 0, 1, ... (round r reads
+// x for r = 0, then y in place); the adjoint applies them in reverse.
+chw_status enqueue_rounds(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y,
+                          void *ws, void *inter0, int inter_is_io0, hipStream_t stream,
+                          const SignArgs &sg)
+{
+    if (!sg.w) return enqueue(p, ds, adj, x, y, inter0, inter_is_io0, stream);
+    for (int i = 0; i < sg.rounds; ++i) {
+        const int r = adj ? sg.rounds - 1 - i : i;
+        chw_status s = enqueue(p, ds, adj, i == 0 ? x : y, y, i == 0 ? inter0 : ws,
+                               i == 0 ? inter_is_io0 : 0, stream, sg.w + (size_t)r * sg.words,
+                               sg.shared, i == 0);
+        if (s != CHW_OK) return s;
+    }
+    return CHW_OK;
+}
+
 bool intervals_overlap(const void *a, size_t alen, const void *b, size_t blen)
 {
     const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
     return x < y + blen && y < x + alen;
 }
 
-chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *stream_v)
+chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *stream_v,
+               const SignArgs &sg = SignArgs{})
 {
     if (!p) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
     if (p->batch == 0 || p->extent == 0) return CHW_OK;
@@ -317,6 +353,10 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
         } else if (!adj && !narrow && x != y) {
             inter = y;  // out-of-place forward: the intermediate goes through y
             inter_is_io = 1;
+            if (sg.w && sg.rounds > 1)
+                return fail(CHW_ERR_INVALID_ARGUMENT,
+                            "several rounds run in place on y and need a workspace of "
+                            "chw_workspace_size() bytes");
         } else {
             return fail(CHW_ERR_INVALID_ARGUMENT,
                         "this call needs a workspace of chw_workspace_size() bytes");
@@ -332,12 +372,15 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
     DeviceState *ds = nullptr;
     if ((s = ensure_tables(p, dev, &ds)) != CHW_OK) return s;
     if (!(p->flags & CHW_FLAG_GRAPH) || p->timing)
-        return enqueue(p, *ds, adj, x, y, inter, inter_is_io, stream);
+        return enqueue_rounds(p, *ds, adj, x, y, ws, inter, inter_is_io, stream, sg);
 
-    // graph replay: capture once per (direction, buffers) on a private stream
+    // graph replay: capture once per (direction, buffers, diagonals) on a
+    // private stream
     GraphEntry *ge = nullptr;
     for (GraphEntry &g : ds->graphs)
-        if (g.adj == adj && g.x == x && g.y == y && g.ws == ws) ge = &g;
+        if (g.adj == adj && g.x == x && g.y == y && g.ws == ws && g.signs == sg.w &&
+            g.sign_shared == sg.shared && g.rounds == sg.rounds)
+            ge = &g;
     if (!ge) {
         hipError_t e;
         if (!ds->cap) {
@@ -350,7 +393,7 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
         }
         e = hipStreamBeginCapture(ds->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        chw_status es = enqueue(p, *ds, adj, x, y, inter, inter_is_io, ds->cap);
+        chw_status es = enqueue_rounds(p, *ds, adj, x, y, ws, inter, inter_is_io, ds->cap, sg);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(ds->cap, &graph);
         if (es != CHW_OK) {
@@ -362,7 +405,7 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-        ds->graphs.push_back(GraphEntry{adj, x, y, ws, exec});
+        ds->graphs.push_back(GraphEntry{adj, x, y, ws, sg.w, sg.shared, sg.rounds, exec});
         ge = &ds->graphs.back();
     }
     hipError_t e = hipGraphLaunch(ge->exec, stream);
@@ -494,6 +537,51 @@ chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
 chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace, void *stream)
 {
     return run(plan, 1, g, y, workspace, stream);
+}
+
+chw_status chw_sign_words(chw_plan_t plan, chw_sign_mode mode, size_t *words)
+{
+    if (!plan || !words) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (mode != CHW_SIGNS_PER_ELEMENT && mode != CHW_SIGNS_SHARED)
+        return fail(CHW_ERR_INVALID_ARGUMENT, "bad sign mode %d", (int)mode);
+    int64_t bits = 0;
+    if (mode == CHW_SIGNS_SHARED) {
+        for (int32_t m : plan->m) bits = std::max(bits, (int64_t)1 << m);
+    } else {
+        bits = plan->extent;
+    }
+    *words = (size_t)((bits + 31) / 32);
+    return CHW_OK;
+}
+
+static chw_status run_signed(chw_plan_t plan, int adj, const void *x, void *y, void *workspace,
+                             const uint32_t *signs, chw_sign_mode mode, int rounds, void *stream)
+{
+    if (!plan) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (!signs) return fail(CHW_ERR_INVALID_ARGUMENT, "signs is NULL");
+    if (reinterpret_cast<uintptr_t>(signs) & 3u)
+        return fail(CHW_ERR_MISALIGNED, "signs must be 4-byte aligned");
+    if (rounds < 1 || rounds > CHW_MAX_ROUNDS)
+        return fail(CHW_ERR_INVALID_ARGUMENT, "rounds = %d outside [1, %d]", rounds, CHW_MAX_ROUNDS);
+    SignArgs sg;
+    chw_status s = chw_sign_words(plan, mode, &sg.words);
+    if (s != CHW_OK) return s;
+    sg.w = signs;
+    sg.shared = mode == CHW_SIGNS_SHARED ? 1 : 0;
+    sg.rounds = rounds;
+    return run(plan, adj, x, y, workspace, stream, sg);
+}
+
+chw_status chw_forward_signed(chw_plan_t plan, const void *x, void *y, void *workspace,
+                              const uint32_t *signs, chw_sign_mode mode, int rounds, void *stream)
+{
+    return run_signed(plan, 0, x, y, workspace, signs, mode, rounds, stream);
+}
+
+chw_status chw_backward_signed(chw_plan_t plan, const void *g, void *y, void *workspace,
+                               const uint32_t *signs, chw_sign_mode mode, int rounds, void *stream)
+{
+    return run_signed(plan, 1, g, y, workspace, signs, mode, rounds, stream);
 }
 
 chw_status chw_plan_destroy(chw_plan_t plan)

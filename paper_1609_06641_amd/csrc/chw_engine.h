@@ -193,6 +193,36 @@ template <> __device__ __forceinline__ uint32_t ortho_scale<uint32_t>(int)
 template <typename C> __device__ __forceinline__ C scale_mul(C v, C s) { return v * s; }
 template <> __device__ __forceinline__ uint32_t scale_mul<uint32_t>(uint32_t v, uint32_t) { return v; }
 
+// Multiplication by a diagonal entry d = +1 (bit 0) or -1 (bit 1): exact in
+// every type (the float sign bit flips; int32 negates, wrapping).
+__device__ __forceinline__ float apply_sign(float v, uint32_t bit)
+{
+    return __uint_as_float(__float_as_uint(v) ^ (bit << 31));
+}
+__device__ __forceinline__ double apply_sign(double v, uint32_t bit)
+{
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)bit << 63));
+}
+__device__ __forceinline__ uint32_t apply_sign(uint32_t v, uint32_t bit)
+{
+    return bit ? 0u - v : v;
+}
+
+// Sign bits of one contiguous 16-byte vector: the V bits starting at the
+// vector's first element (signal position jbase + j when the diagonal is
+// shared by the signals, buffer position g otherwise).  V divides 32 and
+// vectors start at multiples of V, so the bits sit in one word.
+struct SignCtx {
+    const uint32_t *w;  // null: no diagonal
+    int64_t jbase;
+    int shared;
+};
+__device__ __forceinline__ uint32_t sign_bits(const SignCtx &sc, int64_t g, int64_t j)
+{
+    const int64_t b = sc.shared ? sc.jbase + j : g;
+    return sc.w[b >> 5] >> (uint32_t)(b & 31);
+}
+
 // ---------------------------------------------------------------------------
 // the engine
 
@@ -269,23 +299,33 @@ struct Engine {
     template <bool H, typename T>
     static __device__ __forceinline__ void load_contig(C *lds, const T *src, int64_t off,
                                                        int bits, int count,
-                                                       const int64_t *list, int t)
+                                                       const int64_t *list, int t,
+                                                       const SignCtx &sg = SignCtx{nullptr, 0, 0})
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         static_assert(NV >= 1, "tile too small for the vector width");
         C *lb = lds + L::pad(V * t);
         const bool full = (list == nullptr) && ((count << bits) >= N);
+        const int mask = (1 << bits) - 1;
         C vals[NV][V];
         if (full) {
             const T *s = src + off + V * t;
 #pragma unroll
             for (int k = 0; k < NV; ++k) vload<H>(s + V * NT * k, vals[k]);
+            if (sg.w) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    const int e0 = V * t + V * NT * k;
+                    const uint32_t sb = sign_bits(sg, off + e0, e0 & mask);
+#pragma unroll
+                    for (int u = 0; u < V; ++u) vals[k][u] = apply_sign(vals[k][u], (sb >> u) & 1u);
+                }
+            }
 #pragma unroll
             for (int k = 0; k < NV; ++k)
 #pragma unroll
                 for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[k][u];
         } else {
-            const int mask = (1 << bits) - 1;
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 const int e0 = V * t + V * NT * k;
@@ -293,6 +333,11 @@ struct Engine {
                 if (blk < count) {
                     const int64_t g = list ? list[blk] + (e0 & mask) : off + e0;
                     vload<H>(src + g, vals[k]);
+                    if (sg.w) {
+                        const uint32_t sb = sign_bits(sg, g, e0 & mask);
+#pragma unroll
+                        for (int u = 0; u < V; ++u) vals[k][u] = apply_sign(vals[k][u], (sb >> u) & 1u);
+                    }
 #pragma unroll
                     for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[k][u];
                 }
@@ -304,7 +349,8 @@ struct Engine {
     static __device__ __forceinline__ void store_contig(const C *lds, T *dst, int64_t off,
                                                         int bits, int count,
                                                         const int64_t *list, int t,
-                                                        C scale, bool do_scale)
+                                                        C scale, bool do_scale,
+                                                        const SignCtx &sg = SignCtx{nullptr, 0, 0})
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         const C *lb = lds + L::pad(V * t);
@@ -322,6 +368,11 @@ struct Engine {
                     if (do_scale) vals[u] = scale_mul(vals[u], scale);
                 }
                 const int64_t g = (!full && list) ? list[blk] + (e0 & mask) : off + e0;
+                if (sg.w) {
+                    const uint32_t sb = sign_bits(sg, g, e0 & mask);
+#pragma unroll
+                    for (int u = 0; u < V; ++u) vals[u] = apply_sign(vals[u], (sb >> u) & 1u);
+                }
                 vstore<H>(dst + g, vals);
             }
         }
@@ -482,6 +533,13 @@ struct Engine {
     {
         return a.inter_is_io ? it.io_off : it.ws_off;
     }
+    // sign context of a first-pass tile: its rows start at signal position
+    // h0 * 2^(K - CC)
+    template <int CC>
+    static __device__ __forceinline__ SignCtx first_signs(const Item &it, const LaunchArgs &a)
+    {
+        return SignCtx{a.signs, (int64_t)it.h0 << (K - CC), a.sign_shared};
+    }
 
     template <bool ADJ>
     static __device__ __forceinline__ void load_item(const Item &it, const LaunchArgs &a,
@@ -492,20 +550,22 @@ struct Engine {
         switch (it.kind) {
         case KIND_BLOCKS: {
             const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t);
+            if constexpr (!ADJ)
+                load_contig<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t,
+                                      SignCtx{a.signs, 0, a.sign_shared});
             else load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t);
             break;
         }
         case KIND_FIRST_A:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CA>(it, a));
             else load_transp<CA>(lds, inter, first_base<CA>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_B:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CB>(it, a));
             else load_transp<CB>(lds, inter, first_base<CB>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_C:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t);
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CM>(it, a));
             else load_transp<CM>(lds, inter, first_base<CM>(it, a), it.h0, it.rs, t);
             break;
         case KIND_LAST:
@@ -530,12 +590,14 @@ struct Engine {
             const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
             rounds<ADJ>(lds, it.bits, t);
             if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
-            else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
+            else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho,
+                                         SignCtx{a.signs, 0, a.sign_shared});
         } else if constexpr (is_first_kind(KIND)) {
             constexpr int CC = rows_of<KIND>();
             rounds<ADJ>(lds, K - CC, t);
             if constexpr (!ADJ) store_transp<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
-            else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho);
+            else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
+                                         first_signs<CC>(it, a));
         } else {
             rounds<ADJ>(lds, it.bits, t);
             if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, nullptr, t, sc, ortho);
@@ -589,7 +651,7 @@ struct Engine {
 
     template <bool ADJ, int KIND>
     static __device__ __forceinline__ void stream_fetch(const Item &it, const LaunchArgs &a,
-                                                        u32x4 *raw, int t)
+                                                        u32x4 *raw, uint32_t *sw, int t)
     {
         using T = SrcT<ADJ, KIND>;
         constexpr int V = Vec<T>::V, NV = nraw<ADJ, KIND>();
@@ -610,12 +672,26 @@ struct Engine {
             const uint32_t toff = (uint32_t)(V * t);
 #pragma unroll
             for (int k = 0; k < NV; ++k) raw[k] = ld16<src_inter<ADJ, KIND>() ? NT_INTER : NT_IN>(base + V * NT * k + toff);
+            if constexpr (!ADJ && !src_inter<ADJ, KIND>()) {
+                // forward input tiles: sign bits of the diagonal, if any
+                if (a.signs) {
+                    const int bits = KIND == KIND_BLOCKS ? it.bits : K;
+                    const SignCtx sg{a.signs, KIND == KIND_BLOCKS ? 0 : (int64_t)it.h0 << (K - rows_of<KIND>()),
+                                     a.sign_shared};
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        const int e0 = V * t + V * NT * k;
+                        sw[k] = sign_bits(sg, it.io_off + e0, e0 & ((1 << bits) - 1));
+                    }
+                }
+            }
         }
     }
 
     template <bool ADJ, int KIND>
-    static __device__ __forceinline__ void stream_put(const Item &it, const u32x4 *raw, C *lds,
-                                                      int t)
+    static __device__ __forceinline__ void stream_put(const Item &it, const LaunchArgs &a,
+                                                      const u32x4 *raw, const uint32_t *sw,
+                                                      C *lds, int t)
     {
         using T = SrcT<ADJ, KIND>;
         constexpr int V = Vec<T>::V, NV = nraw<ADJ, KIND>();
@@ -625,6 +701,12 @@ struct Engine {
             for (int k = 0; k < NV; ++k) {
                 C vals[V];
                 Vec<T>::decode(raw[k], vals);
+                if constexpr (!src_inter<ADJ, KIND>()) {
+                    if (a.signs) {
+#pragma unroll
+                        for (int u = 0; u < V; ++u) vals[u] = apply_sign(vals[u], (sw[k] >> u) & 1u);
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[u];
             }

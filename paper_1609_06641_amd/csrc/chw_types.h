@@ -82,7 +82,14 @@ struct LaunchArgs {
     const int64_t *list;     // device array of block offsets (ragged BLOCKS)
     int32_t nitems;
     int32_t ortho;           // 1: scale by 2^{-m/2} at the final store
-
+    // Random-sign diagonal D of this call's round, as packed bits (bit set:
+    // the element's sign flips), or null.  Forward: y = H D x, the sign is
+    // applied to the input as it is loaded; adjoint: y = D H^T g, applied to
+    // the output as it is stored.  sign_shared = 1: bit j applies to element
+    // j of every signal; 0: bit e applies to element e of the buffer.
+    const uint32_t *signs;
+    int32_t sign_shared;
+    int32_t pad3;
 };
 
 }  // namespace chw

@@ -10,7 +10,7 @@ namespace chw {
 typedef hipError_t (*ItemsLauncher)(dim3 grid, hipStream_t s, const LaunchArgs &a);
 typedef hipError_t (*TinyLauncher)(dim3 grid, dim3 block, hipStream_t s, const void *in,
                                    void *out, const int64_t *offs, const int32_t *ms,
-                                   int n, int ortho);
+                                   int n, int ortho, const uint32_t *signs, int sign_shared);
 
 // One compiled tile kernel: dtype, tile bits K, register bits LR, the two
 // first-pass row counts (log2) CA and CB, direction.

@@ -323,3 +323,45 @@ def test_plan_invariants_workloads():
     p.check()
     p = chw.Plan([24] * 16, dtype="f32")
     p.check()
+
+
+# ---- signed (random-sign diagonal) entry points: host-side validation --------
+
+def _aligned(buf, align=16):
+    return (ctypes.addressof(buf) + align - 1) & ~(align - 1)
+
+
+def test_sign_words():
+    p = chw.Plan([10, 12, 3], dtype="f32")
+    assert p.sign_words("shared") == (1 << 12) // 32
+    assert p.sign_words("per_element") == (1024 + 4096 + 8 + 31) // 32
+    q = chw.Plan([2], dtype="f32")
+    assert q.sign_words("shared") == 1 and q.sign_words("per_element") == 1
+    n = ctypes.c_size_t()
+    assert chw.load().chw_sign_words(p.handle, 7, ctypes.byref(n)) == 1
+
+
+def test_signed_argument_validation():
+    lib = chw.load()
+    p = chw.Plan([20, 20], dtype="f32")
+    buf = (ctypes.c_char * 256)()
+    a = _aligned(buf)
+    x = ctypes.c_void_p(a)
+    y = ctypes.c_void_p(a + 64)   # distinct, non-overlapping only in address terms
+    s = ctypes.c_void_p(a + 128)
+    fs, bs = lib.chw_forward_signed, lib.chw_backward_signed
+    # NULL plan / NULL signs / misaligned signs / rounds out of range / bad mode
+    assert fs(None, x, x, None, s, 1, 1, None) == 1
+    assert fs(p.handle, x, x, None, None, 1, 1, None) == 1
+    assert fs(p.handle, x, x, None, ctypes.c_void_p(a + 130), 1, 1, None) == 3
+    assert fs(p.handle, x, x, None, s, 1, 0, None) == 1
+    assert fs(p.handle, x, x, None, s, 1, 65, None) == 1
+    assert bs(p.handle, x, x, None, s, 9, 1, None) == 1
+    assert "rounds" in lib.chw_last_error().decode() or lib.chw_last_error()
+    # several rounds of an out-of-place two-pass call need a workspace (the
+    # later rounds run in place on y); checked before any device access
+    big = (ctypes.c_char * ((16 << 20) + 64))()
+    b = _aligned(big)
+    xb, yb = ctypes.c_void_p(b), ctypes.c_void_p(b + (8 << 20))
+    st = fs(p.handle, xb, yb, None, s, 1, 3, None)
+    assert st == 1 and "workspace" in lib.chw_last_error().decode()

@@ -16,7 +16,10 @@ Recipe (all inputs are synthetic; the paper has no datasets):
   * the ragged workload: 20000 log2 sizes drawn uniform in [6, 20] under a
     total budget of 2^30 elements (sequential budgeted draw, see
     ``ragged_log2_sizes``), packed back to back by int64 offsets;
-  * the differentiation workload: a shared random +-1 diagonal.
+  * the differentiation workload: a shared random +-1 diagonal;
+  * the randomized (signed) form: k diagonals of +-1 entries (p = 1/2), round
+    r from the stream [seed, r], packed into uint32 sign bits for the GPU
+    (bit b of a round is bit b % 32 of word b // 32, set for -1).
 """
 
 from .synth import (  # noqa: F401
@@ -28,6 +31,9 @@ from .synth import (  # noqa: F401
     packed_offsets,
     ragged_log2_sizes,
     ragged_values,
+    expand_shared_signs,
+    pack_sign_bits,
     sign_diagonal,
+    sign_rounds,
     to_half_precision,
 )

@@ -135,6 +135,46 @@ def sign_diagonal(seed, n):
     return np.where(g.random(n) < 0.5, -1.0, 1.0).astype(np.float32)
 
 
+def sign_rounds(seed, rounds, n):
+    """`rounds` random +-1 diagonals of length n (p = 1/2 each), int8; round r
+    draws from the stream [seed, r] (round 0 with rounds = 1 equals nothing
+    else in this module)."""
+    out = np.empty((rounds, n), dtype=np.int8)
+    for r in range(rounds):
+        out[r] = np.where(_rng(seed, r).random(n) < 0.5, -1, 1)
+    return out
+
+
+def pack_sign_bits(d):
+    """Pack +-1 entries (last axis) into uint32 words, the layout the GPU
+    library reads: bit b is bit b % 32 of word b // 32, set where the entry
+    is -1.  Rows (rounds) stay separate: shape (..., ceil(n / 32))."""
+    d = np.asarray(d)
+    n = d.shape[-1]
+    words = (n + 31) // 32
+    bits = np.zeros(d.shape[:-1] + (words * 32,), dtype=np.uint8)
+    bits[..., :n] = (d < 0)
+    packed = np.packbits(bits.reshape(d.shape[:-1] + (words, 4, 8)), axis=-1,
+                         bitorder="little")
+    return packed.reshape(d.shape[:-1] + (words, 4)).view(np.uint32).reshape(d.shape[:-1] + (words,))
+
+
+def expand_shared_signs(d_shared, log2_sizes, offsets=None, extent=None):
+    """Per-element +-1 array over a buffer from one diagonal shared by every
+    signal (signal i takes entries 0 .. 2^{m_i} - 1); gaps get +1."""
+    sizes = np.asarray(log2_sizes, dtype=np.int64)
+    if offsets is None:
+        offsets = packed_offsets(sizes)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    extent = int(offsets[-1]) if extent is None else extent
+    d_shared = np.asarray(d_shared)
+    out = np.ones(d_shared.shape[:-1] + (extent,), dtype=d_shared.dtype)
+    for i, k in enumerate(sizes):
+        n = 1 << int(k)
+        out[..., offsets[i]:offsets[i] + n] = d_shared[..., :n]
+    return out
+
+
 @dataclass
 class Workload:
     """A named synthetic workload (shapes of the paper's setting)."""
