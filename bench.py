@@ -118,7 +118,7 @@ def configure(plan, args, x, y, ws, key="plan"):
         cfg = json.loads(args.plan_config)
         if "plan" in cfg or "ragged" in cfg:
             cfg = cfg.get(key, {})
-        for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk", "stream"):
+        for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk", "stream", "pipeline"):
             if k in cfg:
                 plan.set_option(k, int(cfg[k]))
     elif not args.no_tune:

@@ -82,7 +82,19 @@ enum {
                                         hipGraph and replay it               */
     CHW_FLAG_NO_AUTOTUNE = 1u << 1,  /* ignore the tuning cache              */
     CHW_FLAG_PERSISTENT = 1u << 2,   /* one persistent launch (exec 2)        */
-    CHW_FLAG_MULTI_LAUNCH = 1u << 3  /* one launch per HBM pass              */
+    CHW_FLAG_MULTI_LAUNCH = 1u << 3, /* one launch per HBM pass              */
+    /* Coefficient order of the output of chw_forward (and of the input of
+       chw_backward).  Default: dyadic (Paley) order of eq. (1).  The other
+       orders permute the same coefficients (same bits):
+         SEQUENCY: Walsh order, row s of the matrix has s sign changes
+                   (output s = dyadic coefficient gray(s), gray(s) = s ^ s>>1);
+         NATURAL:  Sylvester (Kronecker) order, output k = dyadic coefficient
+                   bitrev_m(k).
+       Exclusive with each other and with CHW_FLAG_PERSISTENT; plans with an
+       order other than dyadic run one workgroup per tile (no prefetching)
+       and one launch per round of a signed call. */
+    CHW_FLAG_ORDER_SEQUENCY = 1u << 4,
+    CHW_FLAG_ORDER_NATURAL = 1u << 5
 };
 
 /* Largest supported log2 signal size (all dtypes except F64). */
@@ -215,6 +227,11 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               tiles; signals up to 2^21; also set by CHW_FLAG_PERSISTENT).
  *               1 (a dependency-counter work queue) is disabled: it gives
  *               CHW_ERR_UNSUPPORTED.
+ *   "pipeline"  1 (with "chunk" > 0): launch j runs the last pass of chunk
+ *               j - 1 together with the first pass of chunk j, both in
+ *               2^15-element tiles, and the chunks' intermediates alternate
+ *               between two workspace slots (0: passes of a chunk in separate
+ *               launches).
  *   "stream"    1 (default): a launch (exec 0) of 2^15-element tiles that
  *               are all full and of one kind runs as a loop over its items,
  *               fetching the next tile's vectors while the current tile runs;

@@ -22,6 +22,8 @@ metrics  -- relative-L2 and exactness comparisons.
 c_oracle -- ctypes loader for the plain-C cascade in chw_oracle.c (same
             algorithm, used where Python is too slow: large parity samples
             and the CPU baseline timing).
+orders   -- the natural (Sylvester) and sequency (Walsh) coefficient orders
+            from their definitions, and the reorderings of the dyadic result.
 signed   -- the randomized form y = H D_k ... H D_1 x with random-sign
             diagonals and its adjoint (not in the paper; each round is the
             cascade above applied to a sign-flipped vector).
@@ -34,4 +36,4 @@ form of the Paley-ordered Hadamard matrix, the library Sylvester matrix,
 Lemma 1 / Theorem 2 counts, orthogonality, Parseval and involution).
 """
 
-from . import dense, cascade, metrics, signed  # noqa: F401
+from . import dense, cascade, metrics, orders, signed  # noqa: F401

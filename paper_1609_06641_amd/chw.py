@@ -23,6 +23,9 @@ FLAG_GRAPH = 1 << 0
 FLAG_NO_AUTOTUNE = 1 << 1
 FLAG_PERSISTENT = 1 << 2
 FLAG_MULTI_LAUNCH = 1 << 3
+FLAG_ORDER_SEQUENCY = 1 << 4
+FLAG_ORDER_NATURAL = 1 << 5
+ORDERS = {"dyadic": 0, "sequency": FLAG_ORDER_SEQUENCY, "natural": FLAG_ORDER_NATURAL}
 SIGN_MODES = {"per_element": 0, "shared": 1}
 
 # symbols declared in include/chw.h: name -> (restype, argtypes)
@@ -106,10 +109,12 @@ class Plan:
 
     offsets: None (packed back to back) or batch + 1 int64 element offsets.
     dtype: 'f32', 'bf16', 'f16', 'i32' or 'f64'.  norm: 'ortho' or 'none'.
+    order: coefficient order 'dyadic' (Paley, eq. 1), 'sequency' (Walsh) or
+    'natural' (Sylvester).
     """
 
     def __init__(self, log2_sizes, dtype="f32", norm="ortho", offsets=None, graph=False,
-                 persistent=False, flags=0):
+                 persistent=False, flags=0, order="dyadic"):
         lib = load()
         import numpy as np
         sizes = np.ascontiguousarray(log2_sizes, dtype=np.int32).ravel()
@@ -124,6 +129,8 @@ class Plan:
                 raise ValueError("offsets needs batch + 1 entries")
         self.offsets = offs_arr
         flags = int(flags) | (FLAG_GRAPH if graph else 0) | (FLAG_PERSISTENT if persistent else 0)
+        flags |= ORDERS[order]
+        self.order = order
         h = _VP()
         _check(lib.chw_plan(ctypes.byref(h), self.batch,
                             sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

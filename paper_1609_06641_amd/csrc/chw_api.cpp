@@ -233,11 +233,14 @@ chw_status mark(chw_plan_t p, DeviceState &ds, int i, hipStream_t stream)
     return CHW_OK;
 }
 
-// Enqueue the launches of one transform (one round) on `stream`; timing
-// events continue from the call's previous ones unless `fresh`.
+// Enqueue the launches of one round (iteration `ri` of `sg.rounds`) on
+// `stream`.  Single-pass launches, the tiny kernel and the persistent launch
+// run every round inside themselves, so they are enqueued with iteration 0
+// only; two-pass launches run one round each.  Timing events continue from
+// the call's previous ones unless `fresh`.
 chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
-                   int inter_is_io, hipStream_t stream, const uint32_t *signs = nullptr,
-                   int sign_shared = 0, bool fresh = true)
+                   int inter_is_io, hipStream_t stream, const SignArgs &sg = SignArgs{},
+                   int ri = 0, bool fresh = true)
 {
     const BuiltPlan &b = p->built;
     chw_status ms;
@@ -246,6 +249,11 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         if ((ms = mark(p, ds, 0, stream)) != CHW_OK) return ms;
     }
     int nev = p->timing ? ds.ev_used : 0;
+    const int k = sg.w ? sg.rounds : 1;
+    // diagonal of this iteration for two-pass launches (the adjoint runs the
+    // rounds backwards)
+    const uint32_t *w_round =
+        sg.w ? sg.w + (size_t)(adj ? k - 1 - ri : ri) * sg.words : nullptr;
     LaunchArgs a{};
     a.in = x;
     a.out = y;
@@ -253,18 +261,27 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     a.inter_is_io = inter_is_io;
     a.list = ds.list;
     a.ortho = p->norm == CHW_ORTHONORMAL ? 1 : 0;
-    a.signs = signs;
-    a.sign_shared = sign_shared;
-    if (!b.tiny_off.empty()) {
+    a.sign_shared = sg.shared;
+    a.sign_words = (int64_t)sg.words;
+    // the dyadic order runs every round of single-pass work inside one launch;
+    // the other orders run one launch per round for every launch
+    const int order = b.cfg.order;
+    const bool fuse = order == ORDER_DYADIC;
+    if (!b.tiny_off.empty() && (ri == 0 || !fuse)) {
         const TinyVariant *tv = find_tiny_variant(p->dt, adj);
         if (!tv) return fail(CHW_ERR_UNSUPPORTED, "no tiny kernel for this dtype");
         const int n = (int)b.tiny_off.size();
         hipError_t e = tv->launch(dim3((n + 255) / 256), dim3(256), stream, x, y, ds.tiny_off,
-                                  ds.tiny_m, n, a.ortho, signs, sign_shared);
+                                  ds.tiny_m, n, a.ortho, fuse ? sg.w : w_round, sg.shared,
+                                  fuse ? k : 1, (int64_t)sg.words, order);
         if (e != hipSuccess) return hip_fail(e, "tiny kernel launch");
         if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
     }
     for (const LaunchRange &r : adj ? b.adj : b.fwd) {
+        const bool in_launch_rounds = fuse && (r.persistent || r.single_pass);
+        if (in_launch_rounds && ri > 0) continue;
+        a.signs = in_launch_rounds ? sg.w : w_round;
+        a.rounds = in_launch_rounds ? k : 1;
         const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
         if (!v || (r.persistent && !v->launch_persistent))
             return fail(CHW_ERR_UNSUPPORTED, "no tile kernel for dtype %d, K=%d, LR=%d", p->dt,
@@ -294,6 +311,8 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         } else if (r.stream >= 1 && r.stream <= 5) {
             const void *fn = v->fn_stream[r.stream - 1];
             e = v->launch_stream[r.stream - 1](dim3(std::min(a.nitems, grid_cap(fn))), stream, a);
+        } else if (order != ORDER_DYADIC) {
+            e = v->launch_order[order - 1](dim3(a.nitems), stream, a);
         } else {
             e = v->launch(dim3(a.nitems), stream, a);
         }
@@ -303,18 +322,22 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     return CHW_OK;
 }
 
-// Every round of a call: the forward applies rounds 0, 1, ... (round r reads
-// x for r = 0, then y in place); the adjoint applies them in reverse.
+// Every round of a call: iteration 0 runs all launches (single-pass tiles
+// do every round); iterations 1.. run the two-pass launches again, reading y
+// in place.  The adjoint walks the rounds backwards.
 chw_status enqueue_rounds(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y,
                           void *ws, void *inter0, int inter_is_io0, hipStream_t stream,
                           const SignArgs &sg)
 {
-    if (!sg.w) return enqueue(p, ds, adj, x, y, inter0, inter_is_io0, stream);
-    for (int i = 0; i < sg.rounds; ++i) {
-        const int r = adj ? sg.rounds - 1 - i : i;
+    const int k = sg.w ? sg.rounds : 1;
+    // later iterations have work when some launch runs one round at a time
+    bool repeat = p->built.cfg.order != ORDER_DYADIC;
+    for (const LaunchRange &r : p->built.fwd)
+        if (!r.persistent && !r.single_pass) repeat = true;
+    for (int i = 0; i < k; ++i) {
+        if (i > 0 && !repeat) break;
         chw_status s = enqueue(p, ds, adj, i == 0 ? x : y, y, i == 0 ? inter0 : ws,
-                               i == 0 ? inter_is_io0 : 0, stream, sg.w + (size_t)r * sg.words,
-                               sg.shared, i == 0);
+                               i == 0 ? inter_is_io0 : 0, stream, sg, i, i == 0);
         if (s != CHW_OK) return s;
     }
     return CHW_OK;
@@ -449,10 +472,15 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
     if (dtype == CHW_I32 && norm != CHW_UNNORMALIZED)
         return fail(CHW_ERR_UNSUPPORTED, "the integer type has only the unnormalized form");
     const uint32_t known = CHW_FLAG_GRAPH | CHW_FLAG_NO_AUTOTUNE | CHW_FLAG_PERSISTENT |
-                           CHW_FLAG_MULTI_LAUNCH;
+                           CHW_FLAG_MULTI_LAUNCH | CHW_FLAG_ORDER_SEQUENCY |
+                           CHW_FLAG_ORDER_NATURAL;
     if (flags & ~known) return fail(CHW_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", flags & ~known);
     if ((flags & CHW_FLAG_PERSISTENT) && (flags & CHW_FLAG_MULTI_LAUNCH))
         return fail(CHW_ERR_INVALID_ARGUMENT, "PERSISTENT and MULTI_LAUNCH are exclusive");
+    if ((flags & CHW_FLAG_ORDER_SEQUENCY) && (flags & CHW_FLAG_ORDER_NATURAL))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "ORDER_SEQUENCY and ORDER_NATURAL are exclusive");
+    if ((flags & (CHW_FLAG_ORDER_SEQUENCY | CHW_FLAG_ORDER_NATURAL)) && (flags & CHW_FLAG_PERSISTENT))
+        return fail(CHW_ERR_UNSUPPORTED, "the persistent launch computes the dyadic order only");
     const int dt = (int)dtype;
     const int maxm = dtype == CHW_F64 ? CHW_MAX_LOG2_F64 : CHW_MAX_LOG2;
     const int es = elem_bytes(dt);
@@ -514,6 +542,8 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
     if (p->extent > (((int64_t)1 << 62) / 8)) return bad(fail(CHW_ERR_OUT_OF_MEMORY, "extent overflows"));
     PlanConfig cfg;
     if (flags & CHW_FLAG_PERSISTENT) cfg.exec = 2;
+    if (flags & CHW_FLAG_ORDER_SEQUENCY) cfg.order = ORDER_SEQUENCY;
+    if (flags & CHW_FLAG_ORDER_NATURAL) cfg.order = ORDER_NATURAL;
     chw_status s = rebuild(p, cfg);
     if (s != CHW_OK) return bad(s);
     *plan = p;
@@ -624,6 +654,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     else if (k == "exec" && (value == 0 || value == 2)) cfg.exec = (int)value;
     else if (k == "chunk" && value >= 0) cfg.chunk = value;
     else if (k == "stream" && (value == 0 || value == 1)) cfg.stream = (int)value;
+    else if (k == "pipeline" && (value == 0 || value == 1)) cfg.pipeline = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
     return rebuild(plan, cfg);
 }
@@ -699,7 +730,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             Split sp;
             bool ok = true;
             for (int32_t m : plan->m)
-                if (m > 15 && !choose_split(m, plan->dt, l1, false, &sp)) ok = false;
+                if (m > 15 && !choose_split(m, plan->dt, l1, false, plan->cfg.order, false, &sp)) ok = false;
             if (ok) l1s.push_back(l1);
         }
     const bool can_persist = maxm <= 21;
@@ -720,6 +751,16 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
                         cands.push_back(c);
                     }
             }
+    // pipelined chunks of 8, 16 or 32 MiB-signals' worth of elements
+    if (has_multi && plan->cfg.order == ORDER_DYADIC)
+        for (int64_t ch : {(int64_t)1 << 23, (int64_t)1 << 24, (int64_t)1 << 25}) {
+            PlanConfig c = plan->cfg;
+            c.exec = 0;
+            c.split_l1 = -1;
+            c.chunk = ch;
+            c.pipeline = 1;
+            cands.push_back(c);
+        }
     if (can_persist)
         for (int lr12 : {5, 6}) {
             PlanConfig c = plan->cfg;
@@ -753,8 +794,8 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (log_enabled())
-            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d stream=%d: %.4f ms\n",
-                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, c.stream, ms / iters);
+            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d stream=%d chunk=%lld pipeline=%d: %.4f ms\n",
+                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, c.stream, (long long)c.chunk, c.pipeline, ms / iters);
         if (ms < best_ms) {
             best_ms = ms;
             best = c;

@@ -174,6 +174,25 @@ __device__ __forceinline__ void vload(const T *p, C *o) { Vec<T>::decode(ld16<NT
 template <bool NT, typename T, typename C>
 __device__ __forceinline__ void vstore(T *p, const C *v) { st16<NT>(p, Vec<T>::encode(v)); }
 
+// one element (for scattered accesses), same conversions as Vec<T>
+__device__ __forceinline__ float get1(const float *p) { return *p; }
+__device__ __forceinline__ uint32_t get1(const uint32_t *p) { return *p; }
+__device__ __forceinline__ double get1(const double *p) { return *p; }
+__device__ __forceinline__ float get1(const bf16s *p) { return __uint_as_float((uint32_t)p->v << 16); }
+__device__ __forceinline__ float get1(const f16s *p) { return (float)__builtin_bit_cast(_Float16, p->v); }
+__device__ __forceinline__ void put1(float *p, float v) { *p = v; }
+__device__ __forceinline__ void put1(uint32_t *p, uint32_t v) { *p = v; }
+__device__ __forceinline__ void put1(double *p, double v) { *p = v; }
+__device__ __forceinline__ void put1(bf16s *p, float v) { p->v = __builtin_bit_cast(uint16_t, (__bf16)v); }
+__device__ __forceinline__ void put1(f16s *p, float v) { p->v = __builtin_bit_cast(uint16_t, (_Float16)v); }
+
+__device__ __forceinline__ int gray_code(int x) { return x ^ (x >> 1); }
+__device__ __forceinline__ int64_t inv_gray_code(int64_t x)
+{
+    x ^= x >> 32; x ^= x >> 16; x ^= x >> 8; x ^= x >> 4; x ^= x >> 2; x ^= x >> 1;
+    return x;
+}
+
 // Orthonormal factor 2^{-m/2}: exact power of two, times fl(2^{-1/2}) when m
 // is odd.
 template <typename C> __device__ __forceinline__ C ortho_scale(int m);
@@ -478,37 +497,162 @@ struct Engine {
         }
     }
 
+    // ---- coefficient orders other than dyadic --------------------------------
+    // Every order is a permutation of the dyadic output: coefficient at output
+    // position o of a block of 2^bits comes from tile element M(o) of the
+    // block (natural storage holds the radix-2 (Sylvester) result):
+    //   dyadic   M(o) = bitrev(o)
+    //   sequency M(o) = bitrev(gray(o))   (dyadic row gray(o) has o sign changes)
+    //   natural  M(o) = o
+    // The adjoint gathers its input through the same map.
+    template <int ORD>
+    static __device__ __forceinline__ int block_src(int o, int bits)
+    {
+        if constexpr (ORD == ORDER_NATURAL) return o;
+        else if constexpr (ORD == ORDER_SEQUENCY) return (int)rbrev((uint32_t)gray_code(o), bits);
+        else return (int)rbrev((uint32_t)o, bits);
+    }
+
+    // single-pass tiles: store (forward) / gather (adjoint) in order ORD
+    template <int ORD, bool LOAD, typename T>
+    static __device__ __forceinline__ void blocks_ordered(C *lds, T *io, int64_t off, int bits,
+                                                          int count, const int64_t *list, int t,
+                                                          C scale, bool do_scale)
+    {
+        constexpr int V = Vec<T>::V, NV = N / (V * NT);
+        const int mask = (1 << bits) - 1;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int o0 = V * t + V * NT * k;
+            const int blk = o0 >> bits;
+            if (blk >= count) continue;
+            const int p0 = o0 & mask;
+            const int64_t g = list ? list[blk] + p0 : off + o0;
+            C vals[V];
+            if constexpr (LOAD) {
+                vload<NT_IN>(io + g, vals);
+#pragma unroll
+                for (int u = 0; u < V; ++u) lds[L::pad((blk << bits) | block_src<ORD>(p0 + u, bits))] = vals[u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    vals[u] = lds[L::pad((blk << bits) | block_src<ORD>(p0 + u, bits))];
+                    if (do_scale) vals[u] = scale_mul(vals[u], scale);
+                }
+                vstore<NT_OUT>(io + g, vals);
+            }
+        }
+    }
+
+    // last-pass tiles of a two-pass signal in order ORD.  The tile holds
+    // blocks bg0 .. bg0 + count - 1 of the signal's 2^L1 blocks of 2^bits.
+    //   sequency: dyadic position P = (bg << bits) | q has sequency index
+    //     invgray(P) = (invgray(bg) << bits) | (invgray(q) ^ (parity(bg) ? mask : 0)),
+    //     so block bg lands as a whole on block invgray(bg);
+    //   natural: the first pass kept block bg = its row element (no bit
+    //     reversal), so element k of block bg is coefficient (k << L1) | bg:
+    //     runs of `count` consecutive blocks, stride 2^L1.
+    template <int ORD, bool LOAD, typename T>
+    static __device__ __forceinline__ void last_ordered(C *lds, T *io, const Item &it, int t,
+                                                        C scale, bool do_scale)
+    {
+        constexpr int V = Vec<T>::V, NV = N / (V * NT);
+        const int b = it.bits, mask = (1 << b) - 1, L1 = it.m - b;
+        const int64_t bg0 = (it.io_off - it.sig_off) >> b;
+        if constexpr (ORD == ORDER_SEQUENCY) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const int o0 = V * t + V * NT * k;
+                const int blk = o0 >> b, s0 = o0 & mask;
+                const int64_t bg = bg0 + blk;
+                const int flipm = (__builtin_popcountll((uint64_t)bg) & 1) ? mask : 0;
+                T *p = io + it.sig_off + (inv_gray_code(bg) << b) + s0;
+                C vals[V];
+                if constexpr (LOAD) vload<NT_IN>(p, vals);
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    const int e = (blk << b) | (int)rbrev((uint32_t)gray_code((s0 + u) ^ flipm), b);
+                    if constexpr (LOAD) {
+                        lds[L::pad(e)] = vals[u];
+                    } else {
+                        vals[u] = lds[L::pad(e)];
+                        if (do_scale) vals[u] = scale_mul(vals[u], scale);
+                    }
+                }
+                if constexpr (!LOAD) vstore<NT_OUT>(p, vals);
+            }
+        } else {
+            // natural: compact output index o = kh * count + blk
+            const int lnb = K - b;                     // log2 count (full tile)
+            if (lnb >= (V == 8 ? 3 : V == 4 ? 2 : 1)) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    const int o0 = V * t + V * NT * k;
+                    const int kh = o0 >> lnb, blk0 = o0 & ((1 << lnb) - 1);
+                    T *p = io + it.sig_off + ((int64_t)kh << L1) + bg0 + blk0;
+                    C vals[V];
+                    if constexpr (LOAD) vload<NT_IN>(p, vals);
+#pragma unroll
+                    for (int u = 0; u < V; ++u) {
+                        const int e = ((blk0 + u) << b) | kh;
+                        if constexpr (LOAD) {
+                            lds[L::pad(e)] = vals[u];
+                        } else {
+                            vals[u] = lds[L::pad(e)];
+                            if (do_scale) vals[u] = scale_mul(vals[u], scale);
+                        }
+                    }
+                    if constexpr (!LOAD) vstore<NT_OUT>(p, vals);
+                }
+            } else {
+                // runs shorter than one vector: element by element
+                for (int o = t; o < N; o += NT) {
+                    const int kh = o >> lnb, blk = o & ((1 << lnb) - 1);
+                    T *p = io + it.sig_off + ((int64_t)kh << L1) + bg0 + blk;
+                    const int e = (blk << b) | kh;
+                    if constexpr (LOAD) {
+                        lds[L::pad(e)] = get1(p);
+                    } else {
+                        C v = lds[L::pad(e)];
+                        if (do_scale) v = scale_mul(v, scale);
+                        put1(p, v);
+                    }
+                }
+            }
+        }
+    }
+
     // ---- transposed phases of a first-pass tile -------------------------------
     // Tile = 2^CC rows of 2^L1 (L1 = K - CC) contiguous elements; element e =
     // (hl << L1) | lo of row h0 + hl sits, after stages 0..L1-1, at position
     // bitrev_L1(lo) * 2^rs + h0 + hl of the signal in the cascade's layout
     // (runs of 2^CC consecutive rows).
-    template <int CC>
+    template <int CC, bool BR = true>
     static __device__ __forceinline__ void store_transp(const C *lds, C *dst, int64_t base,
                                                         int h0, int rs, int t)
     {
         constexpr int V = Vec<C>::V, NV = N / (V * NT);
         static_assert(V <= (1 << CC), "a vector must stay inside one run");
-        const C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
+        const C *lb = lds + L::pad(L::template transp_e<V, CC, BR>(t, 0, 0));
         C *d = dst + base + h0 + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), rs);
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             C vals[V];
 #pragma unroll
             for (int u = 0; u < V; ++u)
-                vals[u] = lb[L::pad(L::template transp_e<V, CC>(0, k, u))];
+                vals[u] = lb[L::pad(L::template transp_e<V, CC, BR>(0, k, u))];
             st16<NT_INTER>(d + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(NT * k), rs),
                            Vec<C>::encode(vals));
         }
     }
 
-    template <int CC>
+    template <int CC, bool BR = true>
     static __device__ __forceinline__ void load_transp(C *lds, const C *src, int64_t base,
                                                        int h0, int rs, int t)
     {
         constexpr int V = Vec<C>::V, NV = N / (V * NT);
         static_assert(V <= (1 << CC), "a vector must stay inside one run");
-        C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
+        C *lb = lds + L::pad(L::template transp_e<V, CC, BR>(t, 0, 0));
         const C *s = src + base + h0 + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), rs);
         C vals[NV][V];
 #pragma unroll
@@ -518,7 +662,7 @@ struct Engine {
         for (int k = 0; k < NV; ++k)
 #pragma unroll
             for (int u = 0; u < V; ++u)
-                lb[L::pad(L::template transp_e<V, CC>(0, k, u))] = vals[k][u];
+                lb[L::pad(L::template transp_e<V, CC, BR>(0, k, u))] = vals[k][u];
     }
 
     // ---- one work item -------------------------------------------------------
@@ -541,10 +685,11 @@ struct Engine {
         return SignCtx{a.signs, (int64_t)it.h0 << (K - CC), a.sign_shared};
     }
 
-    template <bool ADJ>
+    template <bool ADJ, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void load_item(const Item &it, const LaunchArgs &a,
                                                      C *lds, int t)
     {
+        constexpr bool BR = ORD != ORDER_NATURAL;  // first-pass runs bit-reversed
         const S *in = static_cast<const S *>(a.in);
         const C *inter = static_cast<const C *>(a.inter);
         switch (it.kind) {
@@ -553,79 +698,185 @@ struct Engine {
             if constexpr (!ADJ)
                 load_contig<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t,
                                       SignCtx{a.signs, 0, a.sign_shared});
-            else load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t);
+            else if constexpr (ORD == ORDER_DYADIC)
+                load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, list, t);
+            else
+                blocks_ordered<ORD, true>(lds, const_cast<S *>(in), it.io_off, it.bits, it.count,
+                                          list, t, C(1), false);
             break;
         }
         case KIND_FIRST_A:
             if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CA>(it, a));
-            else load_transp<CA>(lds, inter, first_base<CA>(it, a), it.h0, it.rs, t);
+            else load_transp<CA, BR>(lds, inter, first_base<CA>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_B:
             if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CB>(it, a));
-            else load_transp<CB>(lds, inter, first_base<CB>(it, a), it.h0, it.rs, t);
+            else load_transp<CB, BR>(lds, inter, first_base<CB>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_C:
             if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CM>(it, a));
-            else load_transp<CM>(lds, inter, first_base<CM>(it, a), it.h0, it.rs, t);
+            else load_transp<CM, BR>(lds, inter, first_base<CM>(it, a), it.h0, it.rs, t);
             break;
         case KIND_LAST:
             if constexpr (!ADJ) load_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t);
-            else load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, nullptr, t);
+            else if constexpr (ORD == ORDER_DYADIC)
+                load_paley<NT_IN, S>(lds, in, it.io_off, it.bits, it.count, nullptr, t);
+            else
+                last_ordered<ORD, true>(lds, const_cast<S *>(in), it, t, C(1), false);
             break;
         default:
             break;
         }
     }
 
+    // ---- several signed rounds inside one single-pass tile ---------------------
+    // y = H D_k ... H D_1 x (adjoint: D_1 H^T ... D_k H^T g) without leaving
+    // LDS.  After a round the tile holds the round's dyadic-ordered output either
+    // at natural positions or at bit-reversed ones ("flipped").  A round on a
+    // natural tile runs the stages in increasing tile-bit order, on a flipped
+    // tile in decreasing order: both pair the same elements in the same order
+    // as a separate launch would after reloading the output, so the numbers
+    // equal those of one launch per round (FP32 between the rounds).
+    // Multiply every element of the tile's blocks by the scale and by the
+    // sign of the diagonal at its signal position j (the element's position in
+    // its block, bit-reversed when the tile is flipped).  A thread takes 32
+    // consecutive positions j of one block: their sign bits come from one
+    // 64-bit window of the sign words (two 32-bit loads).
+    static __device__ __forceinline__ void lds_sign_scale(const Item &it, const LaunchArgs &a,
+                                                          const uint32_t *w, bool flip,
+                                                          C scale, bool do_scale, C *lds, int t)
+    {
+        const int bits = it.bits;
+        const int gl = bits >= 5 ? 5 : bits;          // log2 positions per group
+        const int groups = N >> gl;
+        for (int q = t; q < groups; q += NT) {
+            const int e0 = q << gl;                   // first tile element of the group
+            const int blk = e0 >> bits;
+            if (blk >= it.count) continue;
+            const int j0 = e0 & ((1 << bits) - 1);
+            const int64_t base = it.list >= 0 ? a.list[it.list + blk]
+                                              : it.io_off + ((int64_t)blk << bits);
+            const int64_t b0 = a.sign_shared ? (int64_t)j0 : base + j0;
+            // the second word only when the group's bits reach into it
+            const bool two = (int)(b0 & 31) + (1 << gl) > 32;
+            const uint64_t win = (uint64_t)w[b0 >> 5] |
+                                 (two ? (uint64_t)w[(b0 >> 5) + 1] << 32 : 0ull);
+            const uint32_t sb = (uint32_t)(win >> (uint32_t)(b0 & 31));
+            // independent reads, then the flips, then the writes
+            int ad[32];
+            C v[32];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                const int j = j0 + u;
+                const int e = (blk << bits) | (flip ? (int)rbrev((uint32_t)j, bits) : j);
+                ad[u] = L::pad(e);
+                if (u < (1 << gl)) v[u] = lds[ad[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                if (do_scale) v[u] = scale_mul(v[u], scale);
+                v[u] = apply_sign(v[u], (sb >> u) & 1u);
+            }
+#pragma unroll
+            for (int u = 0; u < 32; ++u)
+                if (u < (1 << gl)) lds[ad[u]] = v[u];
+        }
+        __syncthreads();
+    }
+
+    template <bool ADJ>
+    static __device__ __forceinline__ void blocks_rounds(const Item &it, const LaunchArgs &a,
+                                                         C *lds, int t)
+    {
+        S *out = static_cast<S *>(a.out);
+        const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
+        const C sc = ortho_scale<C>(it.m);
+        const bool ortho = a.ortho != 0;
+        const int k = a.rounds;
+        bool flip = ADJ;  // the adjoint's tile starts Paley-gathered
+        for (int i = 0; i < k; ++i) {
+            if (!flip) rounds<false>(lds, it.bits, t);
+            else rounds<true>(lds, it.bits, t);
+            flip = !flip;
+            if constexpr (!ADJ) {
+                // the next round's diagonal (round 0's was applied as the tile loaded)
+                if (i + 1 < k)
+                    lds_sign_scale(it, a, a.signs + (int64_t)(i + 1) * a.sign_words, flip, sc,
+                                   ortho, lds, t);
+            } else {
+                // this round's diagonal: rounds run k-1, ..., 0
+                lds_sign_scale(it, a, a.signs + (int64_t)(k - 1 - i) * a.sign_words, flip, sc,
+                               ortho, lds, t);
+            }
+        }
+        // forward: the last round's scale goes with the store; adjoint: done
+        const bool last_scale = !ADJ && ortho;
+        if (flip) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, last_scale);
+        else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, last_scale);
+    }
+
     // stages and store phase of one item of a kind known at compile time
-    template <bool ADJ, int KIND>
+    template <bool ADJ, int KIND, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void finish_kind(const Item &it, const LaunchArgs &a,
                                                        C *lds, int t)
     {
+        constexpr bool BR = ORD != ORDER_NATURAL;  // first-pass runs bit-reversed
         S *out = static_cast<S *>(a.out);
         C *inter = static_cast<C *>(a.inter);
         const C sc = ortho_scale<C>(it.m);
         const bool ortho = a.ortho != 0;
         if constexpr (KIND == KIND_BLOCKS) {
             const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
+            if constexpr (ORD == ORDER_DYADIC) {
+                if (a.rounds > 1) {
+                    blocks_rounds<ADJ>(it, a, lds, t);
+                    return;
+                }
+            }
             rounds<ADJ>(lds, it.bits, t);
-            if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
+            if constexpr (!ADJ && ORD == ORDER_DYADIC)
+                store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
+            else if constexpr (!ADJ)
+                blocks_ordered<ORD, false>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho,
                                          SignCtx{a.signs, 0, a.sign_shared});
         } else if constexpr (is_first_kind(KIND)) {
             constexpr int CC = rows_of<KIND>();
             rounds<ADJ>(lds, K - CC, t);
-            if constexpr (!ADJ) store_transp<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
+            if constexpr (!ADJ) store_transp<CC, BR>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
                                          first_signs<CC>(it, a));
         } else {
             rounds<ADJ>(lds, it.bits, t);
-            if constexpr (!ADJ) store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, nullptr, t, sc, ortho);
+            if constexpr (!ADJ && ORD == ORDER_DYADIC)
+                store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, nullptr, t, sc, ortho);
+            else if constexpr (!ADJ)
+                last_ordered<ORD, false>(lds, out, it, t, sc, ortho);
             else store_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t, C(1), false);
         }
     }
 
-    template <bool ADJ>
+    template <bool ADJ, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void finish_item(const Item &it, const LaunchArgs &a,
                                                        C *lds, int t)
     {
         switch (it.kind) {
-        case KIND_BLOCKS: finish_kind<ADJ, KIND_BLOCKS>(it, a, lds, t); break;
-        case KIND_FIRST_A: finish_kind<ADJ, KIND_FIRST_A>(it, a, lds, t); break;
-        case KIND_FIRST_B: finish_kind<ADJ, KIND_FIRST_B>(it, a, lds, t); break;
-        case KIND_FIRST_C: finish_kind<ADJ, KIND_FIRST_C>(it, a, lds, t); break;
-        case KIND_LAST: finish_kind<ADJ, KIND_LAST>(it, a, lds, t); break;
+        case KIND_BLOCKS: finish_kind<ADJ, KIND_BLOCKS, ORD>(it, a, lds, t); break;
+        case KIND_FIRST_A: finish_kind<ADJ, KIND_FIRST_A, ORD>(it, a, lds, t); break;
+        case KIND_FIRST_B: finish_kind<ADJ, KIND_FIRST_B, ORD>(it, a, lds, t); break;
+        case KIND_FIRST_C: finish_kind<ADJ, KIND_FIRST_C, ORD>(it, a, lds, t); break;
+        case KIND_LAST: finish_kind<ADJ, KIND_LAST, ORD>(it, a, lds, t); break;
         default: break;
         }
     }
 
-    template <bool ADJ>
+    template <bool ADJ, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void run_item(const Item &it, const LaunchArgs &a,
                                                     C *lds, int t)
     {
-        load_item<ADJ>(it, a, lds, t);
+        load_item<ADJ, ORD>(it, a, lds, t);
         __syncthreads();
-        finish_item<ADJ>(it, a, lds, t);
+        finish_item<ADJ, ORD>(it, a, lds, t);
     }
 
     // ---- prefetching (streaming) form ------------------------------------------

@@ -127,14 +127,16 @@ struct Layout {
             return (n & 7) | (g << 3);
         }
     }
-    template <int V, int C>
+    // BR = false: the natural-order variant, run rho holds row element rho
+    // itself (no bit reversal)
+    template <int V, int C, bool BR = true>
     static CHW_HD int transp_e(int t, int k, int u)
     {
         constexpr int L1 = K - C;
         int o = V * transp_q<V, C>(t + NT * k) + u;
         int hl = o & ((1 << C) - 1);
         int rho = o >> C;
-        return (hl << L1) | (int)rbrev((uint32_t)rho, L1);
+        return (hl << L1) | (BR ? (int)rbrev((uint32_t)rho, L1) : rho);
     }
     // element offset (relative to the signal base + h0) of output o, given the
     // run stride 2^rs of the transposed layout

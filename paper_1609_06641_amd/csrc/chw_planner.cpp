@@ -31,7 +31,8 @@ int elem_bytes(int dt)
 
 int compute_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 
-bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out)
+bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool last15,
+                  Split *out)
 {
     struct Opt { int K1, CC, kind; };
     // preference: the widest transposed runs first (2^7 rows = 512-byte runs
@@ -52,13 +53,17 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out)
         out->K1 = o.K1;
         out->CC = o.CC;
         out->kind = o.kind;
-        out->K2 = b <= 12 ? 12 : 15;
+        // the natural order's last pass stores runs of 2^(K2 - b) blocks: the
+        // larger tile gives the longer runs
+        // pipelined chunks run both passes in 2^15-element tiles
+        out->K2 = (b <= 12 && !((order == ORDER_NATURAL || last15) && kmax2 == 15)) ? 12 : 15;
         return true;
     }
     return false;
 }
 
 namespace {
+
 
 Item blank_item()
 {
@@ -83,6 +88,10 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
 {
     BuiltPlan p;
     p.cfg = cfg;
+    if (p.cfg.order != ORDER_DYADIC) {  // one workgroup per tile, one launch per pass
+        p.cfg.stream = 0;
+        if (p.cfg.exec == 2) throw std::invalid_argument("the persistent launch computes the dyadic order only");
+    }
     if (dt == DT_F64) {  // FP64 has only the 2^12-element, 32-register tile kernels
         p.cfg.lr12 = 5;
         p.cfg.single15 = 0;
@@ -131,6 +140,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         for (size_t q = s + 1; q < e; ++q)
             if (off[order[q]] != off[order[s]] + ((int64_t)(q - s) << m)) consecutive = false;
         it.io_off = off[order[s]];
+        it.sig_off = off[order[s]];
         if (!consecutive) {
             it.list = (int32_t)p.list.size();
             for (size_t q = s; q < e; ++q) p.list.push_back(off[order[q]]);
@@ -145,7 +155,8 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         const int m = ms[i];
         if (m <= single_max) continue;
         Split sp;
-        if (!choose_split(m, dt, p.cfg.split_l1, persistent, &sp))
+        const bool pipe = p.cfg.pipeline && p.cfg.chunk > 0 && !persistent;
+        if (!choose_split(m, dt, p.cfg.split_l1, persistent, p.cfg.order, pipe, &sp))
             throw std::invalid_argument("no two-pass split covers log2 size " +
                                         std::to_string(m));
         ++p.n_multi;
@@ -170,6 +181,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             it.h0 = (int32_t)h0;
             it.io_off = off[i] + (h0 << L1);
             it.ws_off = wsb;
+            it.sig_off = off[i];
             ch.first[kidx(sp.K1)].push_back(it);
         }
         const int bpt = 1 << (sp.K2 - b);  // blocks per last-pass tile
@@ -182,6 +194,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             it.count = bpt;
             it.io_off = off[i] + (tl << sp.K2);
             it.ws_off = wsb + (tl << sp.K2);
+            it.sig_off = off[i];
             ch.last[kidx(sp.K2)].push_back(it);
         }
         wsb += (int64_t)1 << m;
@@ -208,6 +221,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
                 it.bits = f.bits;          // L1
                 it.io_off = f.io_off;      // signal base (h0 = 0)
                 it.ws_off = f.ws_off;
+                it.sig_off = f.sig_off;
                 all.push_back(it);
             }
         auto work = [](const Item &it) {
@@ -242,9 +256,60 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     for (int k = 0; k < 2; ++k) {
         LaunchRange r;
         append(blocks[k], k == 0 ? 12 : 15, &r);
+        r.single_pass = 1;
         if (r.end > r.begin) {
             p.fwd.push_back(r);
             p.adj.push_back(r);
+        }
+    }
+    // pipelined chunks: launch 0 = first pass of chunk 0; launch j = last pass
+    // of chunk j - 1 with the first pass of chunk j; the last launch = last
+    // pass of the final chunk.  The adjoint pairs the adjoint first pass of
+    // chunk j - 1 with the adjoint last pass of chunk j; its items are copies
+    // laid out in that order.  Chunk j's intermediate lives in slot j % 2.
+    if (p.cfg.pipeline && p.cfg.chunk > 0 && !persistent && chunks.size() > 1) {
+        int64_t slot = 0;
+        std::vector<int64_t> start(chunks.size(), -1);
+        for (size_t j = 0; j < chunks.size(); ++j) {
+            int64_t lo = INT64_MAX, hi = 0;
+            for (int k = 0; k < 2; ++k)
+                for (const Item &it : chunks[j].last[k]) {
+                    lo = std::min(lo, it.ws_off);
+                    hi = std::max(hi, it.ws_off + ((int64_t)it.count << it.bits));
+                }
+            start[j] = lo == INT64_MAX ? 0 : lo;
+            slot = std::max(slot, hi - start[j]);
+        }
+        if (2 * slot <= (int64_t)p.ws_bound) {
+            for (size_t j = 0; j < chunks.size(); ++j) {
+                const int64_t shift = (int64_t)(j & 1) * slot - start[j];
+                for (int k = 0; k < 2; ++k) {
+                    for (Item &it : chunks[j].first[k]) it.ws_off += shift;
+                    for (Item &it : chunks[j].last[k]) it.ws_off += shift;
+                }
+            }
+            p.ws_elems = (size_t)(2 * slot);
+            auto merged = [&](const std::vector<Item> &a, const std::vector<Item> &b) {
+                std::vector<Item> v(a);
+                v.insert(v.end(), b.begin(), b.end());
+                return v;
+            };
+            const size_t n = chunks.size();
+            for (int dir = 0; dir < 2; ++dir) {
+                for (size_t j = 0; j <= n; ++j) {
+                    // forward: last(j-1) + first(j); adjoint: first(j-1) + last(j)
+                    for (int k = 0; k < 2; ++k) {
+                        const std::vector<Item> none;
+                        const std::vector<Item> &prev = j > 0 ? (dir ? chunks[j - 1].first[k] : chunks[j - 1].last[k]) : none;
+                        const std::vector<Item> &next = j < n ? (dir ? chunks[j].last[k] : chunks[j].first[k]) : none;
+                        LaunchRange r;
+                        append(merged(prev, next), k == 0 ? 12 : 15, &r);
+                        if (r.end > r.begin) (dir ? p.adj : p.fwd).push_back(r);
+                    }
+                }
+            }
+            *out = std::move(p);
+            return;
         }
     }
     for (const Chunk &ch : chunks) {
@@ -300,9 +365,9 @@ std::string describe_plan(const BuiltPlan &p)
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
-                  "\"exec\": %d, \"chunk\": %lld, \"stream\": %d}, ",
+                  "\"exec\": %d, \"chunk\": %lld, \"stream\": %d, \"pipeline\": %d, \"order\": %d}, ",
                   p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec,
-                  (long long)p.cfg.chunk, p.cfg.stream);
+                  (long long)p.cfg.chunk, p.cfg.stream, p.cfg.pipeline, p.cfg.order);
     s += buf;
     s += "\"splits\": [";
     for (size_t i = 0; i < p.splits.size(); ++i) {

@@ -26,6 +26,14 @@ struct PlanConfig {
                         // the batch runs as first pass, last pass on each chunk
                         // in turn, so a chunk's intermediate can stay in the
                         // memory-side cache between its two passes
+    int pipeline = 0;   // 1 (with chunk > 0): overlap the passes of successive
+                        // chunks: launch j runs the last pass of chunk j - 1
+                        // and the first pass of chunk j together (2^15-element
+                        // tiles for both), and the chunks' intermediates take
+                        // turns in two workspace slots, so a chunk's
+                        // intermediate is read back soon after it is written
+    int order = 0;      // coefficient order (Order): set from the plan's
+                        // flags, not a tuning choice
     int stream = 1;     // 1: launches of full 2^15-element tiles of one kind
                         // run the prefetching kernel (a workgroup loops over
                         // items and fetches the next tile while the current
@@ -42,6 +50,8 @@ struct LaunchRange {
     int stream = 0;      // prefetching launch over items of kind stream - 1
                          // (all full tiles, no block lists); 0 = one
                          // workgroup per item
+    int single_pass = 0; // 1: single-pass tiles only (all rounds of a signed
+                         // call run inside the launch)
 };
 
 // Prefetching form of a launch of items [begin, end): 0 when the items are not
@@ -85,7 +95,8 @@ int compute_bytes(int dt);
 
 // Choose the two-pass split for a signal of 2^m elements; false when none of
 // the compiled variants covers m.
-bool choose_split(int m, int dt, int forced_l1, bool k12_only, Split *out);
+bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool last15,
+                  Split *out);
 
 // Build items and launch ranges.  Throws std::bad_alloc on allocation failure,
 // std::invalid_argument when a signal cannot be planned.

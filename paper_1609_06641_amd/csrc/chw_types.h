@@ -30,6 +30,13 @@ enum ItemKind : int32_t {
     KIND_SIGNAL_B = 6,
 };
 
+// Coefficient order of the transform's output (forward) / input (adjoint).
+// Dyadic (Paley) is the order of eq. (1); sequency (Walsh) lists the rows by
+// their number of sign changes, which is the Paley row index read through the
+// inverse Gray code (row p of eq. (1) has invgray(p) sign changes); natural
+// (Sylvester) is the radix-2 Kronecker order, the Paley index bit-reversed.
+enum Order : int { ORDER_DYADIC = 0, ORDER_SEQUENCY = 1, ORDER_NATURAL = 2 };
+
 constexpr bool is_first_kind(int kind)
 {
     return kind == KIND_FIRST_A || kind == KIND_FIRST_B || kind == KIND_FIRST_C;
@@ -60,6 +67,8 @@ constexpr int mid_rows(int K) { return K >= 15 ? K15_CM : K12_CM; }
 struct Item {
     int64_t io_off;
     int64_t ws_off;
+    int64_t sig_off;    // first element of the item's signal (the first
+                        // signal of a BLOCKS tile)
     int32_t kind;
     int32_t bits;       // BLOCKS/LAST: log2 block size (stage bits per block)
     int32_t count;      // BLOCKS/LAST: valid blocks in the tile (>= 1)
@@ -67,7 +76,7 @@ struct Item {
     int32_t rs;         // FIRST: log2 stride of the transposed runs (m - L1)
     int32_t h0;         // FIRST: first row (of 2^L1 elements) of the tile
     int32_t m;          // log2 size of the whole signal (sets the scale)
-    int32_t pad_[5];
+    int32_t pad_[3];
 };
 static_assert(sizeof(Item) == 64, "Item must stay 64 bytes");
 
@@ -89,7 +98,12 @@ struct LaunchArgs {
     // j of every signal; 0: bit e applies to element e of the buffer.
     const uint32_t *signs;
     int32_t sign_shared;
-    int32_t pad3;
+    // Rounds that single-pass tiles, whole-signal (persistent) items and the
+    // tiny kernel run inside this launch (>= 1; more than 1 only with signs):
+    // round r uses the diagonal at signs + r * sign_words.  Two-pass tiles
+    // always run one round per launch.
+    int32_t rounds;
+    int64_t sign_words;
 };
 
 }  // namespace chw

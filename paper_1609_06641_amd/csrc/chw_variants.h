@@ -10,7 +10,8 @@ namespace chw {
 typedef hipError_t (*ItemsLauncher)(dim3 grid, hipStream_t s, const LaunchArgs &a);
 typedef hipError_t (*TinyLauncher)(dim3 grid, dim3 block, hipStream_t s, const void *in,
                                    void *out, const int64_t *offs, const int32_t *ms,
-                                   int n, int ortho, const uint32_t *signs, int sign_shared);
+                                   int n, int ortho, const uint32_t *signs, int sign_shared,
+                                   int rounds, int64_t sign_words, int order);
 
 // One compiled tile kernel: dtype, tile bits K, register bits LR, the two
 // first-pass row counts (log2) CA and CB, direction.
@@ -24,6 +25,8 @@ struct ItemsVariant {
     const void *fn_persistent;
     ItemsLauncher launch_stream[5];   // prefetching form for items of kind
     const void *fn_stream[5];         // BLOCKS, FIRST_A, FIRST_B, LAST, FIRST_C
+    ItemsLauncher launch_order[2];    // one workgroup per item, sequency and
+                                      // natural coefficient order
 };
 
 struct TinyVariant {

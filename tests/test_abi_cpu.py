@@ -222,7 +222,8 @@ def test_layout_selfcheck():
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("opts", [dict(), dict(exec=2), dict(chunk=1 << 20), dict(single15=0),
                                   dict(split_l1=12), dict(exec=2, lr12=5), dict(stream=1),
-                                  dict(stream=0), dict(stream=1, chunk=1 << 22, split_l1=8)])
+                                  dict(stream=0), dict(stream=1, chunk=1 << 22, split_l1=8),
+                                  dict(pipeline=1, chunk=1 << 20), dict(pipeline=1, chunk=1 << 23)])
 def test_plan_invariants_random_ragged(seed, opts):
     rng = np.random.default_rng(seed)
     hi = 22 if opts.get("exec") == 2 else 25
@@ -365,3 +366,46 @@ def test_signed_argument_validation():
     xb, yb = ctypes.c_void_p(b), ctypes.c_void_p(b + (8 << 20))
     st = fs(p.handle, xb, yb, None, s, 1, 3, None)
     assert st == 1 and "workspace" in lib.chw_last_error().decode()
+
+
+# ---- coefficient orders: host-side plan shape --------------------------------
+
+def test_order_flags_and_plan_shape():
+    lib = chw.load()
+    st, h = _plan_raw([10], flags=(1 << 4) | (1 << 5))
+    assert st == 1 and "exclusive" in lib.chw_last_error().decode()
+    st, h = _plan_raw([10], flags=(1 << 4) | (1 << 2))
+    assert st == 2
+    for order, code in (("dyadic", 0), ("sequency", 1), ("natural", 2)):
+        p = chw.Plan([20] * 4 + [13] * 3 + [1], dtype="f32", order=order)
+        d = p.describe()["plan"]
+        assert d["config"]["order"] == code
+        if code:
+            # one workgroup per tile; the natural order's last pass takes the
+            # larger tiles (longer runs of its transposed store)
+            assert d["config"]["stream"] == 0
+            assert all(r["stream"] == 0 for r in d["forward"] + d["backward"])
+        if code == 2:
+            assert d["splits"][0]["K2"] == 15
+        p.check()
+        with pytest.raises(chw.CHWError):
+            q = chw.Plan([20] * 4, dtype="f32", order=order)
+            if code:
+                q.set_option("exec", 2)
+            else:
+                raise chw.CHWError(1, "dyadic accepts exec 2")
+
+
+def test_pipelined_chunks_plan_shape():
+    p = chw.Plan([20] * 8, dtype="f32")
+    p.set_option("chunk", 3 << 20)
+    p.set_option("pipeline", 1)
+    d = p.describe()["plan"]
+    assert d["splits"][0]["K2"] == 15            # both passes in 2^15-element tiles
+    per = (1 << (20 - d["splits"][0]["L1"])) >> d["splits"][0]["rows_log2"]
+    lens = [r["end"] - r["begin"] for r in d["forward"]]
+    assert lens == [3 * per, 3 * 32 + 3 * per, 3 * 32 + 2 * per, 2 * 32]
+    assert len(d["backward"]) == 4
+    assert d["ws_elems"] == 2 * 3 << 20            # two slots of the largest chunk
+    assert p.workspace_size() == 8 << 22           # the reported bound is unchanged
+    p.check()

@@ -193,7 +193,8 @@ def test_split_invariance_bitwise():
                dict(split_l1=8), dict(chunk=1 << 21), dict(exec=2), dict(exec=2, lr12=5),
                dict(stream=0), dict(stream=0, lr12=5), dict(stream=0, split_l1=12, lr15=6),
                dict(stream=0, split_l1=8, chunk=1 << 21), dict(stream=1, split_l1=6),
-               dict(split_l1=10), dict(split_l1=10, stream=0)]
+               dict(split_l1=10), dict(split_l1=10, stream=0),
+               dict(chunk=1 << 20, pipeline=1), dict(chunk=1 << 19, pipeline=1, lr15=6)]
     for cfg in configs:
         p = chw.Plan(sizes, dtype="f32")
         for k, v in cfg.items():
