@@ -144,6 +144,22 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
                     const int64_t *offsets, chw_dtype dtype, chw_norm norm,
                     uint32_t flags);
 
+/*
+ * chw_plan_haar_walsh -- plan the Haar-Walsh transform of eq. (4) for `batch`
+ * signals of 2^m elements packed back to back (signal i at element i 2^m):
+ *     y = diag(1, H_0, H_1, ..., H_{m-1}) w,
+ * the matrix eq. (4) equates with H_m Psi_m^T.  w holds Haar coefficients in
+ * the order of eq. (2) (scaling coefficient, then the detail blocks of 2^k
+ * coefficients, coarsest first); coefficient block [2^k, 2^{k+1}) of every
+ * signal is transformed by H_k and w_0 is copied, so H_m x = (this
+ * transform)(Psi_m x).  The result is an ordinary plan over the ragged batch
+ * of those blocks: chw_forward applies the transform, chw_backward its
+ * transpose, with every rule of chw_plan.  0 <= m <= CHW_MAX_LOG2
+ * (CHW_MAX_LOG2_F64); other arguments as chw_plan.
+ */
+chw_status chw_plan_haar_walsh(chw_plan_t *plan, int64_t batch, int32_t m, chw_dtype dtype,
+                               chw_norm norm, uint32_t flags);
+
 /* Bytes of device workspace a call may need: the FP32 (FP64 for CHW_F64)
  * intermediate between HBM passes of every signal larger than 2^12 elements.
  * The figure does not depend on tuning or options, so a buffer sized from it
@@ -198,6 +214,24 @@ chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace
 chw_status chw_forward_signed(chw_plan_t plan, const void *x, void *y, void *workspace,
                               const uint32_t *signs, chw_sign_mode mode, int rounds,
                               void *stream);
+
+/*
+ * chw_haar_forward -- the Haar wavelet transform alone, y_i = Psi_{m_i} x_i
+ * (eq. 2; the first factor of Theorem 1, "computed for free" by the
+ * cascade): output in the order of eq. (2), scaling coefficient first, then
+ * the detail blocks of 2^k coefficients, coarsest first.  Orthonormal or
+ * unnormalized as the plan says (the unnormalized form drops every
+ * 1/sqrt(2)).  x and y must be distinct (no in-place call); signals above
+ * 2^12 elements need a workspace of chw_workspace_size() bytes (their tile
+ * sums between level passes).  Otherwise as chw_forward.
+ */
+chw_status chw_haar_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
+                            void *stream);
+
+/* chw_haar_backward -- Psi^T g (Haar synthesis, the adjoint and, in the
+ * orthonormal form, the inverse of chw_haar_forward).  Same rules. */
+chw_status chw_haar_backward(chw_plan_t plan, const void *g, void *y, void *workspace,
+                             void *stream);
 
 /* chw_backward_signed -- the adjoint of chw_forward_signed:
  *     y_i = D_1 H^T D_2 H^T ... D_k H^T g_i

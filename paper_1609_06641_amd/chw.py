@@ -47,6 +47,10 @@ SIGNATURES = {
     "chw_forward_signed": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
     "chw_backward_signed": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
     "chw_sign_words": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "chw_haar_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "chw_haar_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "chw_plan_haar_walsh": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
     "chw_layout_selfcheck": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
     "chw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "chw_last_error": (ctypes.c_char_p, []),
@@ -144,6 +148,25 @@ class Plan:
             self.extent = int(offs_arr[-1])
         self._ws = {}
 
+    @classmethod
+    def haar_walsh(cls, batch, m, dtype="f32", norm="ortho", graph=False):
+        """Plan of the Haar-Walsh transform (eq. 4) of `batch` signals of 2^m:
+        y = diag(1, H_0, ..., H_{m-1}) w per signal (w: Haar coefficients)."""
+        import numpy as np
+        lib = load()
+        h = _VP()
+        _check(lib.chw_plan_haar_walsh(ctypes.byref(h), int(batch), int(m), DTYPES[dtype],
+                                       NORMS[norm], FLAG_GRAPH if graph else 0))
+        self = cls.__new__(cls)
+        per = 1 if m == 0 else m + 1
+        sizes = np.tile(np.array([0] + list(range(m)), dtype=np.int32)[:per], int(batch))
+        offs = np.concatenate([(np.int64(i) << m) + np.array([0] + [1 << k for k in range(m)],
+                                                              dtype=np.int64)[:per]
+                               for i in range(int(batch))] + [np.array([int(batch) << m])])
+        self.batch, self.log2_sizes, self.dtype, self.norm = int(sizes.size), sizes, dtype, norm
+        self.offsets, self.order, self.extent, self._ws, self._h = offs, "dyadic", int(batch) << m, {}, h
+        return self
+
     # -- plan queries ---------------------------------------------------------
     @property
     def handle(self):
@@ -224,6 +247,24 @@ class Plan:
             _check(fn(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()), _VP(ws_ptr),
                       _VP(signs.data_ptr()), SIGN_MODES[mode], int(rounds), _VP(sp)))
         return out
+
+    def haar_forward(self, x, out=None, workspace=None, stream=None):
+        """out = Psi x per signal (the Haar transform of eq. 2 alone)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(x)
+        if workspace is None:
+            workspace = self._workspace(x.device, self.workspace_size() > 0)
+        return self._call(load().chw_haar_forward, x, out, workspace, stream, False)
+
+    def haar_backward(self, g, out=None, workspace=None, stream=None):
+        """out = Psi^T g per signal (Haar synthesis)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(g)
+        if workspace is None:
+            workspace = self._workspace(g.device, self.workspace_size() > 0)
+        return self._call(load().chw_haar_backward, g, out, workspace, stream, True)
 
     def sign_words(self, mode="shared"):
         """uint32 words per round of a sign array in layout `mode`."""

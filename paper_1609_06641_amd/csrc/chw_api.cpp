@@ -72,6 +72,7 @@ struct SignArgs {
 
 struct DeviceState {
     int version = -1;              // plan build the tables belong to
+    Item *haar_items = nullptr;    // Haar pyramid table (built once per plan)
     Item *items = nullptr;
     int64_t *list = nullptr;
     int64_t *tiny_off = nullptr;
@@ -82,6 +83,11 @@ struct DeviceState {
     std::vector<hipEvent_t> ev;    // per-launch timing events (option "timing")
     int ev_used = 0;               // events recorded by the last call
 
+    void free_haar()
+    {
+        if (haar_items) (void)hipFree(haar_items);
+        haar_items = nullptr;
+    }
     void free_tables()
     {
         if (items) (void)hipFree(items);
@@ -132,6 +138,8 @@ struct chw_plan_s {
     bool used = false;
     bool timing = false;       // record a HIP event around every launch
     int last_dev = -1;         // device of the last call (for timings)
+    bool haar_built = false;   // the Haar pyramid table (independent of tuning)
+    HaarPlan haar;
     std::mutex mu;
     std::map<int, DeviceState> dev;
 };
@@ -550,6 +558,38 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
     return CHW_OK;
 }
 
+chw_status chw_plan_haar_walsh(chw_plan_t *plan, int64_t batch, int32_t m, chw_dtype dtype,
+                               chw_norm norm, uint32_t flags)
+{
+    if (!plan) return fail(CHW_ERR_INVALID_ARGUMENT, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (batch < 0) return fail(CHW_ERR_INVALID_ARGUMENT, "batch %lld < 0", (long long)batch);
+    if (m < 0 || m > 30) return fail(CHW_ERR_INVALID_ARGUMENT, "m = %d outside [0, 30]", m);
+    // blocks of one signal: w_0 (H_0 = 1), then H_k on [2^k, 2^{k+1}) for
+    // k = 0 .. m-1
+    const int64_t per = m == 0 ? 1 : (int64_t)m + 1;
+    if (batch > ((int64_t)1 << 40) / per) return fail(CHW_ERR_OUT_OF_MEMORY, "batch too large");
+    std::vector<int32_t> sizes;
+    std::vector<int64_t> offs;
+    try {
+        sizes.reserve((size_t)(batch * per));
+        offs.reserve((size_t)(batch * per + 1));
+    } catch (const std::bad_alloc &) {
+        return fail(CHW_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    for (int64_t i = 0; i < batch; ++i) {
+        const int64_t base = i << m;
+        sizes.push_back(0);
+        offs.push_back(base);
+        for (int k = 0; k < m; ++k) {
+            sizes.push_back(k);
+            offs.push_back(base + ((int64_t)1 << k));
+        }
+    }
+    offs.push_back(batch << m);
+    return chw_plan(plan, (int64_t)sizes.size(), sizes.data(), offs.data(), dtype, norm, flags);
+}
+
 chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes)
 {
     if (!plan || !bytes) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
@@ -567,6 +607,83 @@ chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
 chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace, void *stream)
 {
     return run(plan, 1, g, y, workspace, stream);
+}
+
+static chw_status run_haar(chw_plan_t p, int adj, const void *x, void *y, void *ws,
+                           void *stream_v)
+{
+    if (!p) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (p->batch == 0 || p->extent == 0) return CHW_OK;
+    if (!x || !y) return fail(CHW_ERR_INVALID_ARGUMENT, "x and y must be device pointers");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u)
+        return fail(CHW_ERR_MISALIGNED, "x and y must be 16-byte aligned");
+    const size_t bytes = (size_t)p->extent * (size_t)elem_bytes(p->dt);
+    if (intervals_overlap(x, bytes, y, bytes))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "the Haar transform needs distinct x and y");
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (!p->haar_built) {
+            try {
+                build_haar_plan(p->m, p->off, &p->haar);
+            } catch (const std::bad_alloc &) {
+                return fail(CHW_ERR_OUT_OF_MEMORY, "host allocation failed while planning");
+            }
+            p->haar_built = true;
+        }
+    }
+    if (p->haar.ws_elems > 0) {
+        if (!ws)
+            return fail(CHW_ERR_INVALID_ARGUMENT,
+                        "signals above 2^12 need a workspace of chw_workspace_size() bytes");
+        if (reinterpret_cast<uintptr_t>(ws) & 15u)
+            return fail(CHW_ERR_MISALIGNED, "workspace must be 16-byte aligned");
+        const size_t wsb = p->haar.ws_elems * (size_t)compute_bytes(p->dt);
+        if (intervals_overlap(ws, wsb, x, bytes) || intervals_overlap(ws, wsb, y, bytes))
+            return fail(CHW_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
+    }
+    int dev = 0;
+    chw_status s = device_check(&dev);
+    if (s != CHW_OK) return s;
+    const HaarVariant *hv = find_haar_variant(p->dt, adj);
+    if (!hv) return fail(CHW_ERR_UNSUPPORTED, "no Haar kernel for this dtype");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->used = true;
+    p->last_dev = dev;
+    DeviceState &ds = p->dev[dev];
+    if (!ds.haar_items && !p->haar.items.empty())
+        if ((s = upload(&ds.haar_items, p->haar.items)) != CHW_OK) return s;
+    ds.ev_used = 0;
+    if ((s = mark(p, ds, 0, stream)) != CHW_OK) return s;
+    int nev = 1;
+    LaunchArgs a{};
+    a.in = x;
+    a.out = y;
+    a.inter = ws;
+    a.ortho = p->norm == CHW_ORTHONORMAL ? 1 : 0;
+    a.rounds = 1;
+    const int np = (int)p->haar.passes.size();
+    for (int i = 0; i < np; ++i) {
+        const LaunchRange &r = p->haar.passes[adj ? np - 1 - i : i];
+        a.items = ds.haar_items + r.begin;
+        a.nitems = r.end - r.begin;
+        hipError_t e = hv->launch(dim3(a.nitems), stream, a);
+        if (e != hipSuccess) return hip_fail(e, "Haar kernel launch");
+        if ((s = mark(p, ds, nev++, stream)) != CHW_OK) return s;
+    }
+    return CHW_OK;
+}
+
+chw_status chw_haar_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
+                            void *stream)
+{
+    return run_haar(plan, 0, x, y, workspace, stream);
+}
+
+chw_status chw_haar_backward(chw_plan_t plan, const void *g, void *y, void *workspace,
+                             void *stream)
+{
+    return run_haar(plan, 1, g, y, workspace, stream);
 }
 
 chw_status chw_sign_words(chw_plan_t plan, chw_sign_mode mode, size_t *words)
@@ -624,6 +741,7 @@ chw_status chw_plan_destroy(chw_plan_t plan)
         for (auto &kv : plan->dev) {
             if (kv.first != cur) (void)hipSetDevice(kv.first);
             kv.second.free_tables();
+            kv.second.free_haar();
             kv.second.free_events();
             if (kv.second.cap) (void)hipStreamDestroy(kv.second.cap);
         }

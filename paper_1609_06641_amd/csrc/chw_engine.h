@@ -311,6 +311,56 @@ struct Engine {
         }
     }
 
+    // ---- the Haar transform Psi_m alone (eq. 2) --------------------------------
+    // Psi_m is the part of the stages that acts on sums only: at stage b the
+    // pair (e, e | 2^b) belongs to Psi_m iff the low b bits of e are zero.
+    // In register round j those bits are the thread bits below the register
+    // field (one test per thread) and the low register bits (known at compile
+    // time); threads whose test fails hold no pair of the round.
+    template <int j, bool ADJ>
+    static __device__ __forceinline__ void haar_round(C *lds, int nst, int t)
+    {
+        constexpr int lo = L::flo(j), a0 = L::alo(j), a1 = L::ahi(j);
+        if (a0 >= nst) return;  // uniform
+        if ((t & ((1 << lo) - 1)) == 0) {
+            C *base = lds + L::pad(L::round_tbase(j, t));
+            C v[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) v[i] = base[L::pad(L::round_reg(j, i))];
+#pragma unroll
+            for (int s = 0; s < a1 - a0; ++s) {
+                const int bit = ADJ ? a1 - 1 - s : a0 + s;
+                if (bit < nst) {
+                    const int rb = bit - lo;
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if ((i & ((1 << (rb + 1)) - 1)) == 0) {
+                            C a = v[i], b = v[i | (1 << rb)];
+                            v[i] = a + b;
+                            v[i | (1 << rb)] = a - b;
+                        }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) base[L::pad(L::round_reg(j, i))] = v[i];
+        }
+        __syncthreads();
+    }
+
+    template <bool ADJ, int j = 0>
+    static __device__ __forceinline__ void haar_rounds(C *lds, int nst, int t)
+    {
+        if constexpr (j < J) {
+            if constexpr (!ADJ) {
+                haar_round<j, false>(lds, nst, t);
+                haar_rounds<false, j + 1>(lds, nst, t);
+            } else {
+                haar_round<J - 1 - j, true>(lds, nst, t);
+                haar_rounds<true, j + 1>(lds, nst, t);
+            }
+        }
+    }
+
     // ---- contiguous phases ---------------------------------------------------
     // Tile element e <-> memory element (block e >> bits at its base) + (e &
     // (2^bits - 1)).  Blocks are consecutive from `off` unless `list` gives

@@ -5,6 +5,7 @@
 CHW_INST_ITEMS(chw::DT_F64, 12, 5, CHW_K12_CA, 3)
 CHW_INST_PERSIST(chw::DT_F64, 5)
 CHW_INST_TINY(chw::DT_F64)
+CHW_INST_HAAR(chw::DT_F64)
 
 #if !defined(__HIP_DEVICE_COMPILE__)
 namespace chw {
@@ -14,5 +15,6 @@ extern const ItemsVariant items_variants_f64[] = {
 };
 extern const int n_items_variants_f64 = sizeof(items_variants_f64) / sizeof(items_variants_f64[0]);
 extern const TinyVariant tiny_variants_f64[] = {CHW_TINY_VARIANTS(DT_F64)};
+extern const HaarVariant haar_variants_f64[] = {CHW_HAAR_VARIANTS(DT_F64)};
 }  // namespace chw
 #endif

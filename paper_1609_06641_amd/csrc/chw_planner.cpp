@@ -337,6 +337,65 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     *out = std::move(p);
 }
 
+void build_haar_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
+                     HaarPlan *out)
+{
+    HaarPlan h;
+    std::vector<std::vector<Item>> by_pass;
+    int64_t wsb = 0;
+    for (size_t s = 0; s < ms.size(); ++s) {
+        int n = ms[s], p = 0;
+        int64_t src = off[s];  // the pass's vector: x for p = 0, then the workspace
+        while (true) {
+            if ((int)by_pass.size() <= p) by_pass.emplace_back();
+            if (n > 12) {
+                const int64_t tiles = (int64_t)1 << (n - 12);
+                const int64_t next = wsb;
+                wsb += (tiles + 7) & ~(int64_t)7;  // every sums array 32-byte aligned
+                for (int64_t tl = 0; tl < tiles; ++tl) {
+                    Item it = blank_item();
+                    it.kind = p == 0 ? 0 : 1;
+                    it.io_off = src + (tl << 12);
+                    it.sig_off = off[s];
+                    it.m = ms[s];
+                    it.bits = 12;
+                    it.h0 = 12 * p;
+                    it.count = (int32_t)tl;
+                    it.ws_off = next + tl;
+                    by_pass[p].push_back(it);
+                }
+                src = next;
+                n -= 12;
+                ++p;
+            } else {
+                Item it = blank_item();
+                it.kind = p == 0 ? 0 : 1;
+                it.io_off = src;
+                it.sig_off = off[s];
+                it.m = ms[s];
+                it.bits = n;
+                it.h0 = 12 * p;
+                it.count = 0;
+                it.ws_off = -1;
+                by_pass[p].push_back(it);
+                break;
+            }
+        }
+    }
+    for (const std::vector<Item> &v : by_pass) {
+        LaunchRange r;
+        r.K = 12;
+        r.LR = 5;
+        r.begin = (int)h.items.size();
+        h.items.insert(h.items.end(), v.begin(), v.end());
+        r.end = (int)h.items.size();
+        if (h.items.size() > (size_t)0x7fffffff) throw std::bad_alloc();
+        if (r.end > r.begin) h.passes.push_back(r);
+    }
+    h.ws_elems = (size_t)wsb;
+    *out = std::move(h);
+}
+
 int stream_source(const std::vector<Item> &items, int begin, int end, int K, bool adj)
 {
     (void)adj;  // the kernel derives its source (input or intermediate) from the kind

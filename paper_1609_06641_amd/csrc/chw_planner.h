@@ -108,6 +108,17 @@ void build_plan(const std::vector<int32_t> &m, const std::vector<int64_t> &off, 
 bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off, int dt,
                 const BuiltPlan &p, std::string *err);
 
+// The Haar transform Psi_m alone: level passes of 2^12-element tiles (see
+// chw_haar_kernel).  passes[p] covers the tiles of pass p of every signal;
+// the forward runs them in order, the adjoint in reverse.
+struct HaarPlan {
+    std::vector<Item> items;
+    std::vector<LaunchRange> passes;
+    size_t ws_elems = 0;   // tile sums between passes (compute type)
+};
+void build_haar_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
+                     HaarPlan *out);
+
 // JSON description of a built plan.
 std::string describe_plan(const BuiltPlan &p);
 

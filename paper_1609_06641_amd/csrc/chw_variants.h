@@ -34,11 +34,18 @@ struct TinyVariant {
     TinyLauncher launch;
 };
 
+// Haar pyramid tiles (2^12 elements, 2^5 registers per thread).
+struct HaarVariant {
+    int dt, adj;
+    ItemsLauncher launch;
+};
+
 // All variants of all dtypes.
 const ItemsVariant *items_variants(int *count);
 const TinyVariant *tiny_variants(int *count);
 const ItemsVariant *find_items_variant(int dt, int K, int LR, int adj);
 const TinyVariant *find_tiny_variant(int dt, int adj);
+const HaarVariant *find_haar_variant(int dt, int adj);
 
 // Largest log2 size a tiny (one thread per signal) launch handles.
 constexpr int TINY_MAX_LOG2 = 3;

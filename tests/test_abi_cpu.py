@@ -409,3 +409,24 @@ def test_pipelined_chunks_plan_shape():
     assert d["ws_elems"] == 2 * 3 << 20            # two slots of the largest chunk
     assert p.workspace_size() == 8 << 22           # the reported bound is unchanged
     p.check()
+
+
+def test_haar_walsh_plan_shape_and_haar_validation():
+    lib = chw.load()
+    p = chw.Plan.haar_walsh(3, 5, dtype="f32")
+    d = p.describe()
+    assert d["batch"] == 3 * 6 and d["extent"] == 3 * 32
+    p.check()
+    h = ctypes.c_void_p()
+    assert lib.chw_plan_haar_walsh(ctypes.byref(h), 2, 31, 0, 0, 0) == 1
+    assert lib.chw_plan_haar_walsh(ctypes.byref(h), -1, 5, 0, 0, 0) == 1
+    assert lib.chw_plan_haar_walsh(None, 2, 5, 0, 0, 0) == 1
+    # Haar calls: distinct buffers, and a workspace for signals above 2^12
+    q = chw.Plan([14, 3], dtype="f32")
+    buf = (ctypes.c_char * ((1 << 17) + 256))()
+    a = _aligned(buf)
+    x, y = ctypes.c_void_p(a), ctypes.c_void_p(a + 65600)
+    assert lib.chw_haar_forward(q.handle, x, x, None, None) == 1
+    assert lib.chw_haar_forward(q.handle, x, y, None, None) == 1
+    assert "workspace" in lib.chw_last_error().decode()
+    assert lib.chw_haar_backward(None, x, y, None, None) == 1
