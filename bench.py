@@ -40,28 +40,32 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources: a stored traffic figure is valid only for
-    the sources it was measured with."""
+    """Hash of the device-code sources: a stored traffic figure is valid only
+    for the kernels it was measured with (and for the same pass splits, which
+    the profile records too)."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1609_06641_amd", "csrc", "*"))):
-        if f.endswith((".h", ".hip", ".inc", ".cpp")):
+        if f.endswith((".h", ".hip", ".inc")):
             with open(f, "rb") as fh:
                 h.update(os.path.basename(f).encode())
                 h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(path):
-    """Bytes per transform from a committed profile summary, or None."""
-    try:
-        text = open(path).read()
-    except OSError:
+def stored_traffic(path, splits=None):
+    """Traffic per transform from a profiles/ summary, or None when the
+    summary was taken with other kernel sources or other pass splits."""
+    if not os.path.exists(path):
         return None
+    with open(path) as f:
+        text = f.read()
     m = re.search(r"```json\n(.*?)\n```", text, re.S)
     if not m:
         return None
     d = json.loads(m.group(1))
     if d.get("source_hash") != kernel_source_hash():
+        return None
+    if splits is not None and d.get("splits") is not None and d["splits"] != splits:
         return None
     return d.get("traffic_bytes_per_transform")
 
@@ -206,13 +210,55 @@ def bench_headline(args, dev, stream, out):
         "config": {"workload": "plain_2p20_f32: 1024 x 2^20 float32, orthonormal dyadic WHT",
                    "batch": batch, "log2_n": m, "plan": desc["config"],
                    "splits": desc["splits"], "autotuned": not args.no_tune},
-        "roofline": roofline(elems, 8, launches, names, stored_traffic(PROFILE_HEADLINE)),
+        "roofline": roofline(elems, 8, launches, names,
+                             stored_traffic(PROFILE_HEADLINE, desc["splits"])),
         "parity": {"sampled_signals": idx, "max_rel_l2": rel},
         "forward_calls": calls,
     })
+    if not args.no_forms:
+        out["forms"] = bench_forms(args, x, y, m, batch, stream)
     del x, y
     torch.cuda.empty_cache()
     return x_host, m
+
+
+def bench_forms(args, x, y, m, batch, stream):
+    """The other forms on the headline batch (default planner choices, no
+    tuning): the sequency and natural orders, the Haar transform alone
+    (eq. 2), the Haar-Walsh transform (eq. 4) and three signed rounds.
+    Algorithmic bytes: one read and one write of the data."""
+    import torch
+    import workloads
+    from paper_1609_06641_amd import chw
+    elems = batch << m
+    steps = max(3, args.steps // 2)
+    res = {}
+
+    def rec(name, plan, fn, note):
+        ms = time_steps(fn, steps, 2, stream)
+        res[name] = {"ms": round(ms, 4), "Gelem_s": round(elems / (ms / 1e3) / 1e9, 2),
+                     "roofline_frac": round(8 * elems / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "launches_per_call": len(plan.describe()["plan"]["forward"]), "note": note}
+
+    ws = torch.empty(max(chw.Plan([m] * batch).workspace_size(), 16), dtype=torch.uint8,
+                     device=x.device)
+    for order in ("sequency", "natural"):
+        p = chw.Plan([m] * batch, dtype="f32", order=order)
+        rec(order, p, lambda: p.forward(x, out=y, workspace=ws), "exact permutation of the dyadic output")
+        p.close()
+    p = chw.Plan([m] * batch, dtype="f32")
+    rec("haar", p, lambda: p.haar_forward(x, out=y, workspace=ws), "Psi_m x alone (eq. 2)")
+    hw = chw.Plan.haar_walsh(batch, m, dtype="f32")
+    rec("haar_walsh", hw, lambda: hw.forward(x, out=y, workspace=ws), "diag(1, H_0..H_{m-1}) w (eq. 4)")
+    hw.close()
+    k = 3
+    words = workloads.pack_sign_bits(workloads.sign_rounds(2002, k, 1 << m)).reshape(-1).view(np.int32)
+    signs = torch.from_numpy(words.copy()).to(x.device)
+    rec("signed_3_rounds", p, lambda: p.forward_signed(x, signs, "shared", k, out=y, workspace=ws),
+        "y = H D_3 H D_2 H D_1 x, one shared diagonal per round; two-pass signals run one "
+        "launch pair per round")
+    p.close()
+    return res
 
 
 def bench_ragged_bf16(args, dev, stream):
@@ -249,7 +295,7 @@ def bench_ragged_bf16(args, dev, stream):
            "dtype": "bf16 storage, fp32 compute", "plan": d["config"],
            "launches_per_call": len(d["forward"]),
            "roofline": roofline(relems, 4, launches, launch_names(rp),
-                                stored_traffic(PROFILE_RAGGED)),
+                                stored_traffic(PROFILE_RAGGED, d["splits"])),
            "parity": {"log2_sizes": [int(ks[i]) for i in sel], "max_rel_l2": max(rels)}}
     log("bf16 ragged: %.3f ms/step" % rms)
     del xb, yb, ws
@@ -317,6 +363,7 @@ def run_other(args, dev, stream):
     out = {"workload": w.name, "ms_per_step": round(ms, 4),
            "Gelem_s": round(elems / (ms / 1e3) / 1e9, 2),
            "roofline": roofline(elems, bpe, launches, names, None),
+           "splits": plan.describe()["plan"]["splits"],
            "plan": plan.describe()["plan"]["config"],
            "forward_calls": args.warmup + args.steps * (1 if args.no_launch_timing else 2)}
     if k > 0:
@@ -413,7 +460,12 @@ def summarize(args):
         if "chw::" in k or "copyBuffer" in k:
             lines.append("| `%s` | %d | %.0f | %.0f |" % (k[:90], len(fetch[k]), sum(fetch[k]) / len(fetch[k]),
                                                          sum(write.get(k, [0])) / max(1, len(write.get(k, [0])))))
-    summary = {"source_hash": kernel_source_hash(), "calls": args.calls,
+    splits = None
+    if args.bench_json and os.path.exists(args.bench_json):
+        with open(args.bench_json) as f:
+            bj = json.loads(f.read().strip().splitlines()[-1])
+        splits = bj.get("config", {}).get("splits", bj.get("splits"))
+    summary = {"source_hash": kernel_source_hash(), "calls": args.calls, "splits": splits,
                "fetch_factor": ff, "write_factor": fw,
                "traffic_bytes_per_transform": traffic,
                "kernels_avg_us": {k[:90]: round(sum(v) / len(v), 2) for k, v in stats.items()
@@ -439,6 +491,8 @@ def main():
     ap.add_argument("--plan-config", help="JSON planner options instead of autotuning")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other orders / Haar / signed forms on the headline batch")
     ap.add_argument("--no-launch-timing", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--workload", default="plain_2p20_f32")
@@ -451,6 +505,8 @@ def main():
     ap.add_argument("--title", default="profile")
     ap.add_argument("--cmd", action="append")
     ap.add_argument("--out")
+    ap.add_argument("--bench-json", help="with --summarize: the JSON line of the traced run "
+                                         "(records the pass splits the profile covers)")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)

@@ -41,6 +41,12 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
                         {15, K15_CM, KIND_FIRST_C}, {12, K12_CM, KIND_FIRST_C},
                         {15, K15_CB, KIND_FIRST_B}, {12, K12_CB, KIND_FIRST_B}};
     const int kmax2 = (dt == DT_F64 || k12_only) ? 12 : 15;
+    // the natural order's last pass also stores runs, of 2^(K2 - b) blocks:
+    // it takes the larger last-pass tile and the split whose shorter run is
+    // longest; pipelined chunks run both passes in 2^15-element tiles
+    const bool natural = order == ORDER_NATURAL;
+    bool found = false;
+    int best_score = -1;
     for (const Opt &o : opts) {
         if (o.K1 == 15 && (dt == DT_F64 || k12_only)) continue;
         if (o.kind == KIND_FIRST_C && k12_only) continue;  // whole-signal items: A or B
@@ -48,18 +54,20 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
         if (forced_l1 > 0 && L1 != forced_l1) continue;
         const int b = m - L1;                 // levels left for the second pass
         if (b < o.CC || b > kmax2) continue;  // each first-pass tile needs 2^CC rows
+        const int K2 = (b <= 12 && !((natural || last15) && kmax2 == 15)) ? 12 : 15;
+        const int score = natural ? std::min(o.CC, K2 - b) : 0;
+        if (found && score <= best_score) continue;
+        found = true;
+        best_score = score;
         out->m = m;
         out->L1 = L1;
         out->K1 = o.K1;
         out->CC = o.CC;
         out->kind = o.kind;
-        // the natural order's last pass stores runs of 2^(K2 - b) blocks: the
-        // larger tile gives the longer runs
-        // pipelined chunks run both passes in 2^15-element tiles
-        out->K2 = (b <= 12 && !((order == ORDER_NATURAL || last15) && kmax2 == 15)) ? 12 : 15;
-        return true;
+        out->K2 = K2;
+        if (!natural) break;  // first valid option in preference order
     }
-    return false;
+    return found;
 }
 
 namespace {
