@@ -104,9 +104,13 @@ def roofline(elems, bytes_per_elem, launches_ms, kernel_names, traffic):
     algo = elems * bytes_per_elem
     achieved = algo / (total_ms / 1e3) / 1e9
     dom = int(np.argmax(launches_ms)) if launches_ms else 0
+    # measured HBM fraction: the PMC bytes of every pass over the same time
+    measured = None if traffic is None else round(
+        traffic / (total_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "measured_hbm_frac": measured,
         "kernel": kernel_names[dom] if kernel_names else None,
         "algorithmic_bytes_per_transform": algo,
         "launches": [{"kernel": n, "ms": round(t, 4),
@@ -154,10 +158,17 @@ def cpu_baseline(x_host, m, sample):
     t0 = time.perf_counter()
     c_oracle.chw_rows(xs, threads=threads)
     dt = time.perf_counter() - t0
+    one = min(32, sample)
+    t0 = time.perf_counter()
+    c_oracle.chw_rows(xs[:one], threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(sample * (1 << m) / dt / 1e9, 5), "unit": "Gelem/s",
             "cores": threads, "kind": "oracle",
             "sample": "%d of the %d signals of 2^%d, float64 plain-C cascade, %.2f s"
-                      % (sample, x_host.shape[0], m, dt)}
+                      % (sample, x_host.shape[0], m, dt),
+            "single_thread": {"value": round(one * (1 << m) / dt1 / 1e9, 5),
+                              "unit": "Gelem/s", "cores": 1,
+                              "sample": "%d signals of 2^%d, %.2f s" % (one, m, dt1)}}
 
 
 def copy_calibration(gib, dev, stream, steps):
