@@ -27,6 +27,8 @@ orders   -- the natural (Sylvester) and sequency (Walsh) coefficient orders
 signed   -- the randomized form y = H D_k ... H D_1 x with random-sign
             diagonals and its adjoint (not in the paper; each round is the
             cascade above applied to a sign-flipped vector).
+philox   -- Philox4x64-10 random-sign words (a published counter-based
+            generator, not the paper's), as the device generates them.
 
 Every function names the passage of the paper it follows.  Nothing here is
 "parity unpinned": each function is pinned by tests marked ``not gpu`` against
@@ -36,4 +38,4 @@ form of the Paley-ordered Hadamard matrix, the library Sylvester matrix,
 Lemma 1 / Theorem 2 counts, orthogonality, Parseval and involution).
 """
 
-from . import dense, cascade, metrics, orders, signed  # noqa: F401
+from . import dense, cascade, metrics, orders, philox, signed  # noqa: F401
