@@ -268,6 +268,18 @@ def bench_forms(args, x, y, m, batch, stream):
     rec("signed_3_rounds", p, lambda: p.forward_signed(x, signs, "shared", k, out=y, workspace=ws),
         "y = H D_3 H D_2 H D_1 x, one shared diagonal per round; two-pass signals run one "
         "launch pair per round")
+    # one round with a fresh per-element diagonal drawn on the device every call
+    pe_words = torch.empty(p.sign_words("per_element"), dtype=torch.int32, device=x.device)
+    seed = [0]
+
+    def device_signed():
+        seed[0] += 1
+        p.philox_signs(seed[0], 1, "per_element", out=pe_words)
+        p.forward_signed(x, pe_words, "per_element", 1, out=y, workspace=ws)
+    rec("signed_device_signs", p, device_signed,
+        "y = H D x with D (one bit per element) drawn by Philox4x64-10 on the device each call")
+    gen_ms = time_steps(lambda: p.philox_signs(7, 1, "per_element", out=pe_words), steps, 2, stream)
+    res["signed_device_signs"]["philox_ms"] = round(gen_ms, 4)
     p.close()
     return res
 

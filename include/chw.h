@@ -245,6 +245,30 @@ chw_status chw_backward_signed(chw_plan_t plan, const void *g, void *y, void *wo
  * for CHW_SIGNS_SHARED, ceil(offsets[batch] / 32) for CHW_SIGNS_PER_ELEMENT. */
 chw_status chw_sign_words(chw_plan_t plan, chw_sign_mode mode, size_t *words);
 
+/*
+ * chw_philox_signs -- generate the sign arrays of chw_forward_signed /
+ * chw_backward_signed on the device from the Philox4x64-10 counter-based
+ * generator (J. Salmon et al., "Parallel random numbers: as easy as 1, 2,
+ * 3", SC 2011; each sign is +1 or -1 with probability 1/2):
+ *     word w of round r (0-based) = 32-bit word (w mod 8) of the Philox4x64-10
+ *     block with counter (floor(w / 8), r, 0, 0) and key (seed, 0), where the
+ *     block's 64-bit outputs o_0..o_3 give words 2i (low half of o_i) and
+ *     2i + 1 (high half).
+ * The words depend only on (seed, r, w), so any thread, call or host can
+ * regenerate any sign.
+ *
+ *   seed    the generator key.
+ *   rounds  1 .. CHW_MAX_ROUNDS.
+ *   signs   device array of rounds * W uint32 words (W = chw_sign_words(plan,
+ *           mode)), 4-byte aligned, owned by the caller; round r is written at
+ *           words [r W, (r + 1) W), the bits past the last element included.
+ *   stream  as chw_forward.
+ * Errors: plan or signs NULL, bad mode or rounds -> CHW_ERR_INVALID_ARGUMENT;
+ * signs misaligned -> CHW_ERR_MISALIGNED; no GPU -> CHW_ERR_NO_DEVICE.
+ */
+chw_status chw_philox_signs(chw_plan_t plan, chw_sign_mode mode, uint64_t seed, int rounds,
+                            uint32_t *signs, void *stream);
+
 /* Release a plan and its device tables and graphs.  NULL is a no-op.  The
  * caller must have synchronized every stream the plan was used on. */
 chw_status chw_plan_destroy(chw_plan_t plan);

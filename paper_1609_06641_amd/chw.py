@@ -47,6 +47,8 @@ SIGNATURES = {
     "chw_forward_signed": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
     "chw_backward_signed": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
     "chw_sign_words": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "chw_philox_signs": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, _VP,
+                                        _VP]),
     "chw_haar_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "chw_haar_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "chw_plan_haar_walsh": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int32,
@@ -271,6 +273,23 @@ class Plan:
         n = ctypes.c_size_t()
         _check(load().chw_sign_words(self.handle, SIGN_MODES[mode], ctypes.byref(n)))
         return int(n.value)
+
+    def philox_signs(self, seed, rounds=1, mode="shared", out=None, device=None, stream=None):
+        """int32 tensor of rounds x sign_words(mode) packed sign bits drawn on the
+        device from Philox4x64-10 with key (seed, 0) (see chw_philox_signs)."""
+        torch = _torch()
+        need = int(rounds) * self.sign_words(mode)
+        if out is None:
+            dev = torch.device("cuda") if device is None else torch.device(device)
+            out = torch.empty(max(need, 1), dtype=torch.int32, device=dev)
+        self._sign_check(out, mode, rounds)
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        sp = stream if isinstance(stream, int) else stream.cuda_stream
+        _check(load().chw_philox_signs(self.handle, SIGN_MODES[mode],
+                                       ctypes.c_uint64(int(seed) & (2**64 - 1)), int(rounds),
+                                       _VP(out.data_ptr()), _VP(sp)))
+        return out
 
     def _sign_check(self, signs, mode, rounds):
         torch = _torch()

@@ -701,6 +701,29 @@ chw_status chw_sign_words(chw_plan_t plan, chw_sign_mode mode, size_t *words)
     return CHW_OK;
 }
 
+chw_status chw_philox_signs(chw_plan_t plan, chw_sign_mode mode, uint64_t seed, int rounds,
+                            uint32_t *signs, void *stream)
+{
+    if (!plan) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (!signs) return fail(CHW_ERR_INVALID_ARGUMENT, "signs is NULL");
+    if (reinterpret_cast<uintptr_t>(signs) & 3u)
+        return fail(CHW_ERR_MISALIGNED, "signs must be 4-byte aligned");
+    if (rounds < 1 || rounds > CHW_MAX_ROUNDS)
+        return fail(CHW_ERR_INVALID_ARGUMENT, "rounds = %d outside [1, %d]", rounds, CHW_MAX_ROUNDS);
+    size_t words = 0;
+    chw_status s = chw_sign_words(plan, mode, &words);
+    if (s != CHW_OK) return s;
+    if (words == 0) return CHW_OK;
+    int dev = 0;
+    if ((s = device_check(&dev)) != CHW_OK) return s;
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = launch_philox_signs(signs, (int64_t)words, rounds, seed, cus,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "Philox sign kernel launch");
+    return CHW_OK;
+}
+
 static chw_status run_signed(chw_plan_t plan, int adj, const void *x, void *y, void *workspace,
                              const uint32_t *signs, chw_sign_mode mode, int rounds, void *stream)
 {

@@ -47,6 +47,11 @@ const ItemsVariant *find_items_variant(int dt, int K, int LR, int adj);
 const TinyVariant *find_tiny_variant(int dt, int adj);
 const HaarVariant *find_haar_variant(int dt, int adj);
 
+// Fills rounds x words sign words from Philox4x64-10 (chw_philox.hip):
+// word w of round r at out[r * words + w].
+hipError_t launch_philox_signs(uint32_t *out, int64_t words, int rounds, uint64_t seed,
+                               int cus, hipStream_t s);
+
 // Largest log2 size a tiny (one thread per signal) launch handles.
 constexpr int TINY_MAX_LOG2 = 3;
 

@@ -430,3 +430,19 @@ def test_haar_walsh_plan_shape_and_haar_validation():
     assert lib.chw_haar_forward(q.handle, x, y, None, None) == 1
     assert "workspace" in lib.chw_last_error().decode()
     assert lib.chw_haar_backward(None, x, y, None, None) == 1
+
+
+def test_philox_signs_argument_validation():
+    # every argument check comes before any device access (status 5 = no device)
+    lib = chw.load()
+    p = chw.Plan([10, 12], dtype="f32")
+    buf = (ctypes.c_char * 64)()
+    a = _aligned(buf)
+    ph = lib.chw_philox_signs
+    assert ph(None, 1, 5, 1, ctypes.c_void_p(a), None) == 1
+    assert ph(p.handle, 1, 5, 1, None, None) == 1
+    assert ph(p.handle, 1, 5, 1, ctypes.c_void_p(a + 2), None) == 3
+    assert ph(p.handle, 1, 5, 0, ctypes.c_void_p(a), None) == 1
+    assert ph(p.handle, 1, 5, 65, ctypes.c_void_p(a), None) == 1
+    assert ph(p.handle, 9, 5, 1, ctypes.c_void_p(a), None) == 1
+    assert ph(p.handle, 1, 5, 1, ctypes.c_void_p(a + 4), None) == 5
