@@ -39,13 +39,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRANSFORM_SOURCES = ("chw_engine.h", "chw_layout.h", "chw_types.h", "chw_kernels.inc")
+
+
 def kernel_source_hash():
-    """Hash of the device-code sources: a stored traffic figure is valid only
-    for the kernels it was measured with (and for the same pass splits, which
-    the profile records too)."""
+    """Hash of the sources of the transform kernels: a stored traffic figure
+    is valid only for the kernels it was measured with (and for the same pass
+    splits, which the profile records too)."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1609_06641_amd", "csrc", "*"))):
-        if f.endswith((".h", ".hip", ".inc")):
+        b = os.path.basename(f)
+        if b in TRANSFORM_SOURCES or (b.startswith("chw_kernels_") and b.endswith(".hip")):
             with open(f, "rb") as fh:
                 h.update(os.path.basename(f).encode())
                 h.update(fh.read())
@@ -280,6 +284,15 @@ def bench_forms(args, x, y, m, batch, stream):
         "y = H D x with D (one bit per element) drawn by Philox4x64-10 on the device each call")
     gen_ms = time_steps(lambda: p.philox_signs(7, 1, "per_element", out=pe_words), steps, 2, stream)
     res["signed_device_signs"]["philox_ms"] = round(gen_ms, 4)
+    del pe_words
+    # the factor-by-factor node evaluation of Sec. 4: one launch per factor
+    nws = torch.empty(p.nodes_workspace_size(), dtype=torch.uint8, device=x.device)
+    for name, chunk in (("nodes", 0), ("nodes_chunked", 32)):
+        rec(name, p, lambda: p.nodes_forward(x, out=y, workspace=nws, chunk=chunk),
+            "eq. (3) factor by factor: %d node launches of a full read and write each%s"
+            % (m, "" if chunk == 0 else ", %d signals at a time" % chunk))
+        res[name]["launches_per_call"] = m + sum(1 for r in range(m) if (m if r == 0 else m - r) > 12)
+    del nws
     p.close()
     return res
 

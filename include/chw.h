@@ -233,6 +233,40 @@ chw_status chw_haar_forward(chw_plan_t plan, const void *x, void *y, void *works
 chw_status chw_haar_backward(chw_plan_t plan, const void *g, void *y, void *workspace,
                              void *stream);
 
+/*
+ * chw_nodes_forward -- y_i = H_m x_i evaluated factor by factor, the way the
+ * parallel scheme of Sec. 4 distributes the cascade over processing nodes:
+ * one launch ("node") per factor of eq. (3), node 0 applying Psi_m (eq. 2) to
+ * every signal and node r (1 <= r <= m - 1) applying F_r = I_{r-1} (x)
+ * diag(I_{m-r}, Psi_{m-r}) -- the Haar transforms of size 2^{m-r} on the
+ * upper halves -- while passing the rest of the stream through.  Every Haar
+ * level scales by fl(2^{-1/2}) as eq. (2) writes it, so results equal
+ * chw_forward's up to rounding.  Each node reads and writes the whole
+ * vector: this entry point exists to measure the paper's decomposition
+ * against the stage-grouped kernels of chw_forward, which it does not
+ * replace.
+ *
+ *   plan       orthonormal, dyadic CHW_F32 plan of equal sizes 2^m,
+ *              1 <= m <= 24, packed back to back (offsets NULL or i 2^m);
+ *              other plans give CHW_ERR_UNSUPPORTED.
+ *   x, y       distinct, non-overlapping device buffers of batch 2^m floats,
+ *              4-byte aligned.
+ *   workspace  chw_nodes_workspace_size() bytes (the stream between nodes
+ *              and the chunk sums of the large Haar transforms), 4-byte
+ *              aligned, not overlapping x or y.
+ *   chunk      0: every node runs over the whole batch before the next one;
+ *              c > 0: the batch runs c signals at a time, all m nodes on one
+ *              chunk before the next, so a node reads its predecessor's output
+ *              while it is still cached (the streaming between nodes).
+ *   stream     as chw_forward.
+ */
+chw_status chw_nodes_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
+                             int64_t chunk, void *stream);
+
+/* Workspace bytes of chw_nodes_forward for any chunk: 4 (batch 2^m +
+ * batch 2^{m-12}) (the second term for m > 12 only). */
+chw_status chw_nodes_workspace_size(chw_plan_t plan, size_t *bytes);
+
 /* chw_backward_signed -- the adjoint of chw_forward_signed:
  *     y_i = D_1 H^T D_2 H^T ... D_k H^T g_i
  * (rounds in reverse order, each diagonal applied to its round's output as

@@ -31,6 +31,7 @@ SOURCES = [
     "chw_kernels_i32.hip",
     "chw_kernels_f64.hip",
     "chw_philox.hip",
+    "chw_nodes.hip",
     "chw_registry.cpp",
     "chw_planner.cpp",
     "chw_api.cpp",

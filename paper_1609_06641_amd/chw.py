@@ -49,6 +49,8 @@ SIGNATURES = {
     "chw_sign_words": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "chw_philox_signs": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, _VP,
                                         _VP]),
+    "chw_nodes_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "chw_nodes_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     "chw_haar_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "chw_haar_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "chw_plan_haar_walsh": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int32,
@@ -289,6 +291,31 @@ class Plan:
         _check(load().chw_philox_signs(self.handle, SIGN_MODES[mode],
                                        ctypes.c_uint64(int(seed) & (2**64 - 1)), int(rounds),
                                        _VP(out.data_ptr()), _VP(sp)))
+        return out
+
+    def nodes_workspace_size(self):
+        """Bytes of workspace chw_nodes_forward needs."""
+        n = ctypes.c_size_t()
+        _check(load().chw_nodes_workspace_size(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def nodes_forward(self, x, out=None, workspace=None, chunk=0, stream=None):
+        """out = H x per signal evaluated factor by factor (one launch per factor
+        of eq. (3), the node decomposition of Sec. 4); for comparison with
+        forward(), which computes the same transform."""
+        torch = _torch()
+        self._tensor_check(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._tensor_check(out, "out")
+        if workspace is None:
+            workspace = torch.empty(max(self.nodes_workspace_size(), 16), dtype=torch.uint8,
+                                    device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        sp = stream if isinstance(stream, int) else stream.cuda_stream
+        _check(load().chw_nodes_forward(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()),
+                                        _VP(workspace.data_ptr()), int(chunk), _VP(sp)))
         return out
 
     def _sign_check(self, signs, mode, rounds):

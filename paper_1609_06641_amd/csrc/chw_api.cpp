@@ -724,6 +724,82 @@ chw_status chw_philox_signs(chw_plan_t plan, chw_sign_mode mode, uint64_t seed, 
     return CHW_OK;
 }
 
+// ---- the factor-by-factor node evaluation (Sec. 4) ----------------------------
+
+static chw_status nodes_shape(chw_plan_t p, int *m_out)
+{
+    if (!p) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (p->dt != DT_F32 || p->norm != CHW_ORTHONORMAL || p->cfg.order != ORDER_DYADIC)
+        return fail(CHW_ERR_UNSUPPORTED,
+                    "the node evaluation takes orthonormal dyadic CHW_F32 plans only");
+    const int m = p->batch > 0 ? p->m[0] : 1;
+    if (m < 1 || m > 24) return fail(CHW_ERR_UNSUPPORTED, "the node evaluation takes 1 <= m <= 24");
+    for (int64_t i = 0; i < p->batch; ++i)
+        if (p->m[i] != m || p->off[i] != (i << m))
+            return fail(CHW_ERR_UNSUPPORTED,
+                        "the node evaluation takes equal sizes packed back to back");
+    *m_out = m;
+    return CHW_OK;
+}
+
+static size_t nodes_ws_elems(int64_t signals, int m)
+{
+    return (size_t)(signals << m) + (m > 12 ? (size_t)(signals << (m - 12)) : 0);
+}
+
+chw_status chw_nodes_workspace_size(chw_plan_t plan, size_t *bytes)
+{
+    if (!bytes) return fail(CHW_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    int m = 0;
+    chw_status s = nodes_shape(plan, &m);
+    if (s != CHW_OK) return s;
+    *bytes = nodes_ws_elems(plan->batch, m) * sizeof(float);
+    return CHW_OK;
+}
+
+chw_status chw_nodes_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
+                             int64_t chunk, void *stream)
+{
+    int m = 0;
+    chw_status s = nodes_shape(plan, &m);
+    if (s != CHW_OK) return s;
+    if (chunk < 0) return fail(CHW_ERR_INVALID_ARGUMENT, "chunk = %lld < 0", (long long)chunk);
+    const int64_t batch = plan->batch;
+    if (batch == 0) return CHW_OK;
+    if (!x || !y || !workspace)
+        return fail(CHW_ERR_INVALID_ARGUMENT, "x, y and workspace must be device pointers");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) |
+         reinterpret_cast<uintptr_t>(workspace)) & 3u)
+        return fail(CHW_ERR_MISALIGNED, "x, y and workspace must be 4-byte aligned");
+    const int64_t per = chunk > 0 && chunk < batch ? chunk : batch;
+    const size_t bytes = (size_t)(batch << m) * sizeof(float);
+    const size_t wsb = nodes_ws_elems(per, m) * sizeof(float);
+    if (intervals_overlap(x, bytes, y, bytes) || intervals_overlap(workspace, wsb, x, bytes) ||
+        intervals_overlap(workspace, wsb, y, bytes))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "x, y and workspace must not overlap");
+    int dev = 0;
+    if ((s = device_check(&dev)) != CHW_OK) return s;
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float *ws = static_cast<float *>(workspace);
+    float *sums = ws + (per << m);
+    for (int64_t c0 = 0; c0 < batch; c0 += per) {
+        const int64_t nb = std::min(per, batch - c0);
+        const float *in = static_cast<const float *>(x) + (c0 << m);
+        float *yc = static_cast<float *>(y) + (c0 << m);
+        // node r writes y when m - 1 - r is even, else the workspace, so that
+        // the last node lands in y and no node reads what it writes
+        for (int r = 0; r < m; ++r) {
+            float *out = ((m - 1 - r) % 2 == 0) ? yc : ws;
+            hipError_t e = launch_node(in, out, sums, nb, m, r, cus, st);
+            if (e != hipSuccess) return hip_fail(e, "node kernel launch");
+            in = out;
+        }
+    }
+    return CHW_OK;
+}
+
 static chw_status run_signed(chw_plan_t plan, int adj, const void *x, void *y, void *workspace,
                              const uint32_t *signs, chw_sign_mode mode, int rounds, void *stream)
 {

@@ -52,6 +52,12 @@ const HaarVariant *find_haar_variant(int dt, int adj);
 hipError_t launch_philox_signs(uint32_t *out, int64_t words, int rounds, uint64_t seed,
                                int cus, hipStream_t s);
 
+// One node of the factor-by-factor evaluation (chw_nodes.hip): factor r of
+// eq. (3) (r = 0: Psi_m) on `batch` packed FP32 signals of 2^m, in -> out;
+// `sums` holds batch * 2^{m-12} floats when m > 12.
+hipError_t launch_node(const float *in, float *out, float *sums, int64_t batch, int m, int r,
+                       int cus, hipStream_t st);
+
 // Largest log2 size a tiny (one thread per signal) launch handles.
 constexpr int TINY_MAX_LOG2 = 3;
 

@@ -446,3 +446,29 @@ def test_philox_signs_argument_validation():
     assert ph(p.handle, 1, 5, 65, ctypes.c_void_p(a), None) == 1
     assert ph(p.handle, 9, 5, 1, ctypes.c_void_p(a), None) == 1
     assert ph(p.handle, 1, 5, 1, ctypes.c_void_p(a + 4), None) == 5
+
+
+def test_nodes_validation():
+    # plan restrictions and argument checks come before any device access
+    lib = chw.load()
+    buf = (ctypes.c_char * 256)()
+    a = _aligned(buf)
+    x, y, w = ctypes.c_void_p(a), ctypes.c_void_p(a + 64), ctypes.c_void_p(a + 128)
+    n = ctypes.c_size_t()
+    p = chw.Plan([20] * 4, dtype="f32")
+    assert lib.chw_nodes_workspace_size(p.handle, ctypes.byref(n)) == 0
+    assert n.value == 4 * (4 * (1 << 20) + 4 * (1 << 8))
+    q = chw.Plan([10] * 3, dtype="f32")
+    assert q.nodes_workspace_size() == 4 * 3 * 1024
+    for bad in (chw.Plan([20] * 2, dtype="bf16"), chw.Plan([10, 11], dtype="f32"),
+                chw.Plan([25], dtype="f32"), chw.Plan([8] * 2, dtype="f32", order="sequency"),
+                chw.Plan([8] * 2, dtype="i32", norm="none"),
+                chw.Plan([8] * 2, dtype="f32", offsets=[0, 512, 1024])):
+        assert lib.chw_nodes_workspace_size(bad.handle, ctypes.byref(n)) == 2
+        assert lib.chw_nodes_forward(bad.handle, x, y, w, 0, None) == 2
+    assert lib.chw_nodes_forward(None, x, y, w, 0, None) == 1
+    assert lib.chw_nodes_forward(q.handle, None, y, w, 0, None) == 1
+    assert lib.chw_nodes_forward(q.handle, x, y, None, 0, None) == 1
+    assert lib.chw_nodes_forward(q.handle, x, y, w, -1, None) == 1
+    assert lib.chw_nodes_forward(q.handle, ctypes.c_void_p(a + 2), y, w, 0, None) == 3
+    assert lib.chw_nodes_forward(q.handle, x, x, w, 0, None) == 1

@@ -115,3 +115,38 @@ def test_ragged_full(dtype, persistent):
     nx = np.sqrt(np.bincount(seg, weights=xin ** 2))
     ny = np.sqrt(np.bincount(seg, weights=yout ** 2))
     assert np.max(np.abs(ny - nx) / nx) <= (1e-5 if dtype == "f32" else 8e-3)
+
+
+@pytest.mark.parametrize("m", [23, 25, 26, 27])
+def test_largest_sizes_f32(m):
+    # the largest signals a plan takes (2^27 = CHW_MAX_LOG2), one signal,
+    # out of place and in place, whole signal against the oracle
+    torch = gu.torch()
+    xh = workloads.float_signals(900 + m, 1, m)
+    ref = gu.oracle_packed(xh.astype(np.float64).reshape(-1), [m], threads=1)
+    p = chw.Plan([m], dtype="f32")
+    x = torch.from_numpy(xh.reshape(-1)).cuda()
+    y = p.forward(x)
+    t = x.clone()
+    p.forward(t, out=t)
+    back = p.backward(y)
+    torch.cuda.synchronize()
+    for got in (y, t):
+        assert metrics.rel_l2(got.double().cpu().numpy(), ref) <= 1e-5
+    assert metrics.rel_l2(back.double().cpu().numpy(), xh.reshape(-1).astype(np.float64)) <= 2e-5
+
+
+def test_largest_size_i32_wraps_exactly():
+    # 2^27 int32 inputs in [1, 127]: the DC coefficient (about 2^33) wraps,
+    # the others stay in range; every element equals the int64 oracle modulo
+    # 2^32
+    torch = gu.torch()
+    m = 27
+    xh = workloads.int_signals(927, 1, m, lo=1, hi=127).reshape(-1)
+    ref = gu.oracle_packed(xh.astype(np.int64), [m], threads=1)
+    p = chw.Plan([m], dtype="i32", norm="none")
+    y = p.forward(gu.dev_tensor(xh, "i32"))
+    torch.cuda.synchronize()
+    wrapped = (ref & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+    assert np.abs(ref).max() >= 2 ** 31
+    assert np.array_equal(y.cpu().numpy(), wrapped)
