@@ -246,9 +246,11 @@ chw_status mark(chw_plan_t p, DeviceState &ds, int i, hipStream_t stream)
 // run every round inside themselves, so they are enqueued with iteration 0
 // only; two-pass launches run one round each.  Timing events continue from
 // the call's previous ones unless `fresh`.
+// `phase` selects launches: 0 all; 1 the tiny kernel, single-pass and
+// first-pass launches; 2 the last-pass launches.
 chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
                    int inter_is_io, hipStream_t stream, const SignArgs &sg = SignArgs{},
-                   int ri = 0, bool fresh = true)
+                   int ri = 0, bool fresh = true, int phase = 0)
 {
     const BuiltPlan &b = p->built;
     chw_status ms;
@@ -275,7 +277,7 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     // the other orders run one launch per round for every launch
     const int order = b.cfg.order;
     const bool fuse = order == ORDER_DYADIC;
-    if (!b.tiny_off.empty() && (ri == 0 || !fuse)) {
+    if (!b.tiny_off.empty() && (ri == 0 || !fuse) && phase != 2) {
         const TinyVariant *tv = find_tiny_variant(p->dt, adj);
         if (!tv) return fail(CHW_ERR_UNSUPPORTED, "no tiny kernel for this dtype");
         const int n = (int)b.tiny_off.size();
@@ -288,6 +290,10 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     for (const LaunchRange &r : adj ? b.adj : b.fwd) {
         const bool in_launch_rounds = fuse && (r.persistent || r.single_pass);
         if (in_launch_rounds && ri > 0) continue;
+        if (phase != 0) {
+            const bool last = b.items[r.begin].kind == KIND_LAST;
+            if ((phase == 1) == last) continue;
+        }
         a.signs = in_launch_rounds ? sg.w : w_round;
         a.rounds = in_launch_rounds ? k : 1;
         const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
@@ -330,14 +336,80 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     return CHW_OK;
 }
 
+// The round-boundary launch between rounds ri - 1 and ri of a signed forward
+// call: KIND_TURN tiles read round ri - 1's intermediate `src` and write round
+// ri's intermediate `dst` (the workspace and y take turns).
+chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, void *src, int src_io, void *dst,
+                        int dst_io, void *y, hipStream_t stream, const SignArgs &sg, int ri)
+{
+    const BuiltPlan &b = p->built;
+    int nev = p->timing ? ds.ev_used : 0;
+    chw_status ms;
+    for (const LaunchRange &r : b.turn) {
+        const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, 0);
+        if (!v || !v->launch_turn)
+            return fail(CHW_ERR_UNSUPPORTED, "no round-boundary kernel for dtype %d, LR=%d", p->dt,
+                        r.LR);
+        LaunchArgs a{};
+        a.out = y;
+        a.inter = src;
+        a.inter_is_io = src_io;
+        a.inter2 = dst;
+        a.inter2_is_io = dst_io;
+        a.items = ds.items + r.begin;
+        a.nitems = r.end - r.begin;
+        a.list = ds.list;
+        a.ortho = p->norm == CHW_ORTHONORMAL ? 1 : 0;
+        a.signs = sg.w + (size_t)ri * sg.words;
+        a.sign_shared = sg.shared;
+        a.sign_words = (int64_t)sg.words;
+        a.rounds = 1;
+        hipError_t e;
+        if (r.stream) {
+            int &cap = ds.grid_cap[v->fn_turn_stream];
+            if (cap == 0) {
+                int per_cu = 0, dev = 0, cus = 0;
+                (void)hipGetDevice(&dev);
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->fn_turn_stream, v->nt,
+                                                                 0) != hipSuccess || per_cu < 1) {
+                    (void)hipGetLastError();
+                    per_cu = 1;
+                }
+                (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+                cap = per_cu * std::max(1, cus);
+            }
+            e = v->launch_turn_stream(dim3(std::min(a.nitems, cap)), stream, a);
+        } else {
+            e = v->launch_turn(dim3(a.nitems), stream, a);
+        }
+        if (e != hipSuccess) return hip_fail(e, "round-boundary kernel launch");
+        if ((ms = mark(p, ds, nev++, stream)) != CHW_OK) return ms;
+    }
+    return CHW_OK;
+}
+
 // Every round of a call: iteration 0 runs all launches (single-pass tiles
 // do every round); iterations 1.. run the two-pass launches again, reading y
-// in place.  The adjoint walks the rounds backwards.
+// in place.  The adjoint walks the rounds backwards.  A signed forward call
+// whose plan has round-boundary tiles instead runs: the first pass of round
+// 0 (with the single-pass work), one round-boundary launch per later round,
+// and the last pass of the final round -- k + 1 passes over the two-pass
+// signals instead of 2k.
 chw_status enqueue_rounds(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y,
                           void *ws, void *inter0, int inter_is_io0, hipStream_t stream,
                           const SignArgs &sg)
 {
     const int k = sg.w ? sg.rounds : 1;
+    if (!adj && k > 1 && !p->built.turn.empty() && ws) {
+        // round i's intermediate: the workspace for even i, y for odd i
+        chw_status s = enqueue(p, ds, 0, x, y, ws, 0, stream, sg, 0, true, 1);
+        for (int i = 1; i < k && s == CHW_OK; ++i)
+            s = enqueue_turn(p, ds, (i - 1) % 2 ? y : ws, (i - 1) % 2, i % 2 ? y : ws, i % 2, y,
+                             stream, sg, i);
+        if (s != CHW_OK) return s;
+        return enqueue(p, ds, 0, y, y, (k - 1) % 2 ? y : ws, (k - 1) % 2, stream, sg, k - 1,
+                       false, 2);
+    }
     // later iterations have work when some launch runs one round at a time
     bool repeat = p->built.cfg.order != ORDER_DYADIC;
     for (const LaunchRange &r : p->built.fwd)
@@ -872,6 +944,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     else if (k == "chunk" && value >= 0) cfg.chunk = value;
     else if (k == "stream" && (value == 0 || value == 1)) cfg.stream = (int)value;
     else if (k == "pipeline" && (value == 0 || value == 1)) cfg.pipeline = (int)value;
+    else if (k == "turn" && (value == 0 || value == 1)) cfg.turn = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
     return rebuild(plan, cfg);
 }

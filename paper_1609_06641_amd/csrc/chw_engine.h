@@ -875,7 +875,9 @@ struct Engine {
         C *inter = static_cast<C *>(a.inter);
         const C sc = ortho_scale<C>(it.m);
         const bool ortho = a.ortho != 0;
-        if constexpr (KIND == KIND_BLOCKS) {
+        if constexpr (KIND == KIND_TURN) {
+            if constexpr (!ADJ && ORD == ORDER_DYADIC) finish_turn(it, a, lds, t);
+        } else if constexpr (KIND == KIND_BLOCKS) {
             const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
             if constexpr (ORD == ORDER_DYADIC) {
                 if (a.rounds > 1) {
@@ -903,6 +905,86 @@ struct Engine {
             else if constexpr (!ADJ)
                 last_ordered<ORD, false>(lds, out, it, t, sc, ortho);
             else store_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t, C(1), false);
+        }
+    }
+
+    // ---- a round boundary of a two-pass signal (signed rounds, forward) -------
+    // A 2^15-element tile of consecutive last-pass blocks of round r holds,
+    // after the round's remaining stages, round r's output for 2^15
+    // consecutive positions -- 2^CC whole first-pass rows of round r + 1.
+    // turn_round0 takes round r + 1's first register round straight from that
+    // state: thread t reads the 2^LR consecutive output positions its register
+    // round covers through the last pass's Paley map, scales them, applies
+    // round r + 1's diagonal, runs the round's stages and writes them back in
+    // natural order; the remaining register rounds and the transposed store
+    // follow as in a first-pass tile.  Operands and their order are those of a
+    // last-pass store, a reload and a first-pass load, so the numbers are the
+    // same, with one HBM pass fewer.
+    //
+    // Sign bits of n <= 64 consecutive positions starting at bit b0 of the
+    // diagonal (as many words as the window touches).
+    static __device__ __forceinline__ uint64_t sign_window(const uint32_t *w, int64_t b0, int n)
+    {
+        const int64_t w0 = b0 >> 5, w1 = (b0 + n - 1) >> 5;
+        uint64_t lo = w[w0];
+        if (w1 > w0) lo |= (uint64_t)w[w0 + 1] << 32;
+        const int sh = (int)(b0 & 31);
+        uint64_t r = lo >> sh;
+        if (w1 > w0 + 1) r |= (uint64_t)w[w0 + 2] << (64 - sh);
+        return r;
+    }
+
+    static __device__ __forceinline__ void turn_round0(const Item &it, const LaunchArgs &a,
+                                                       int nst, C *lds, int t)
+    {
+        const int bits = it.bits;
+        const int o0 = t << LR;  // register round 0: positions o0 .. o0 + R - 1
+        const int rb = L::pad(brev_low(o0, bits));
+        C v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = lds[rb + L::pad(brev_low(i, bits))];
+        __syncthreads();
+        const C sc = ortho_scale<C>(it.m);
+        const bool ortho = a.ortho != 0;
+        const uint64_t sb = a.signs ? sign_window(a.signs, a.sign_shared ? it.io_off - it.sig_off + o0
+                                                                         : it.io_off + o0, R)
+                                    : 0ull;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            C x = v[i];
+            if (ortho) x = scale_mul(x, sc);
+            v[i] = apply_sign(x, (uint32_t)(sb >> i) & 1u);
+        }
+#pragma unroll
+        for (int bit = 0; bit < LR; ++bit)
+            if (bit < nst) bfly(v, bit);
+        C *wb = lds + L::pad(o0);
+#pragma unroll
+        for (int i = 0; i < R; ++i) wb[L::pad(i)] = v[i];
+        __syncthreads();
+    }
+
+    template <int CC>
+    static __device__ __forceinline__ void finish_turn_cc(const Item &it, const LaunchArgs &a,
+                                                          C *lds, int t)
+    {
+        static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
+        rounds<false>(lds, it.bits, t);
+        turn_round0(it, a, K - CC, lds, t);
+        rounds<false, 1>(lds, K - CC, t);
+        const int64_t base = a.inter2_is_io ? it.sig_off
+                                            : it.ws_off - ((int64_t)it.h0 << (K - CC));
+        store_transp<CC, true>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
+    }
+
+    static __device__ __forceinline__ void finish_turn(const Item &it, const LaunchArgs &a,
+                                                       C *lds, int t)
+    {
+        if constexpr (K >= 15) {
+            const int cc = K - (it.m - it.bits);
+            if (cc == CA) finish_turn_cc<CA>(it, a, lds, t);
+            else if (cc == CM) finish_turn_cc<CM>(it, a, lds, t);
+            else if (cc == CB) finish_turn_cc<CB>(it, a, lds, t);
         }
     }
 
@@ -935,7 +1017,7 @@ struct Engine {
     // item runs its stages and stores.  The tile's source is either the input
     // (storage type S) or the intermediate (compute type C):
     //   forward BLOCKS / FIRST : input, contiguous        -> LDS contiguous
-    //   forward LAST           : intermediate, contiguous -> LDS contiguous
+    //   forward LAST / TURN    : intermediate, contiguous -> LDS contiguous
     //   adjoint BLOCKS / LAST  : input, contiguous        -> LDS Paley positions
     //   adjoint FIRST          : intermediate, transposed -> LDS transposed
     // and the LDS placement is exactly the one of load_item.  Global addresses
@@ -943,7 +1025,7 @@ struct Engine {
     template <bool ADJ, int KIND>
     static constexpr bool src_inter()
     {
-        return ADJ ? is_first_kind(KIND) : KIND == KIND_LAST;
+        return ADJ ? is_first_kind(KIND) : (KIND == KIND_LAST || KIND == KIND_TURN);
     }
     template <bool ADJ, int KIND>
     using SrcT = typename std::conditional<src_inter<ADJ, KIND>(), C, S>::type;

@@ -111,6 +111,51 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         }
         return true;
     };
+    // round-boundary tiles: each a full 2^15-element tile of one two-pass
+    // signal whose first pass has a compiled 2^15-element row count, inside
+    // its signal and the workspace; together they cover every two-pass
+    // signal exactly once
+    if (!p.turn.empty()) {
+        std::vector<std::pair<int64_t, int64_t>> tv;
+        for (const LaunchRange &r : p.turn) {
+            if (r.K != 15 || r.persistent || (r.stream != 0 && r.stream != 1 + KIND_TURN)) {
+                *err = "round-boundary launch with the wrong tile or form";
+                return false;
+            }
+            for (int k = r.begin; k < r.end; ++k) {
+                const Item &it = p.items[k];
+                const int L1 = it.m - it.bits, cc = 15 - L1;
+                if (it.kind != KIND_TURN || ((int64_t)it.count << it.bits) != ((int64_t)1 << 15) ||
+                    (cc != K15_CA && cc != K15_CM && cc != K15_CB) || it.rs != it.bits ||
+                    ((it.io_off - it.sig_off) & 32767) != 0 ||
+                    (int64_t)it.h0 != ((it.io_off - it.sig_off) >> L1)) {
+                    *err = "malformed round-boundary tile";
+                    return false;
+                }
+                if (it.ws_off < 0 || (size_t)(it.ws_off + 32768) > p.ws_elems ||
+                    it.io_off + 32768 > it.sig_off + ((int64_t)1 << it.m)) {
+                    *err = "round-boundary tile outside its signal or the workspace";
+                    return false;
+                }
+                tv.push_back({it.io_off, it.io_off + 32768});
+            }
+        }
+        std::sort(tv.begin(), tv.end());
+        int64_t need = 0, have = 0;
+        for (size_t i = 0; i < tv.size(); ++i) {
+            if (i && tv[i].first < tv[i - 1].second) {
+                *err = "round-boundary tiles overlap";
+                return false;
+            }
+            have += tv[i].second - tv[i].first;
+        }
+        for (size_t i = 0; i < batch; ++i)
+            if (ms[i] > 15) need += (int64_t)1 << ms[i];
+        if (have != need || p.n_multi == 0) {
+            *err = "round-boundary tiles do not cover the two-pass signals";
+            return false;
+        }
+    }
     for (int dir = 0; dir < 2; ++dir) {
         const std::vector<LaunchRange> &L = dir ? p.adj : p.fwd;
         for (const LaunchRange &r : L) {

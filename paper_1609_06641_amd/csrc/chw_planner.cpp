@@ -159,6 +159,8 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
 
     // ---- multi-pass signals --------------------------------------------------
     int64_t wsb = 0;
+    std::vector<Item> turn_items;
+    bool turn_ok = p.cfg.turn && p.cfg.order == ORDER_DYADIC && (dt == DT_F32 || dt == DT_I32);
     for (int64_t i = 0; i < batch; ++i) {
         const int m = ms[i];
         if (m <= single_max) continue;
@@ -204,6 +206,24 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             it.ws_off = wsb + (tl << sp.K2);
             it.sig_off = off[i];
             ch.last[kidx(sp.K2)].push_back(it);
+        }
+        // round boundary tiles: 2^15 consecutive positions = 2^CC first-pass
+        // rows of the next round (first pass in 2^15-element tiles only)
+        if (sp.K1 != 15) turn_ok = false;
+        if (turn_ok) {
+            for (int64_t tl = 0; tl < ((int64_t)1 << (m - 15)); ++tl) {
+                Item it = blank_item();
+                it.kind = KIND_TURN;
+                it.bits = b;
+                it.m = m;
+                it.count = 1 << (15 - b);
+                it.io_off = off[i] + (tl << 15);
+                it.ws_off = wsb + (tl << 15);
+                it.sig_off = off[i];
+                it.h0 = (int32_t)(tl << sp.CC);
+                it.rs = b;
+                turn_items.push_back(it);
+            }
         }
         wsb += (int64_t)1 << m;
     }
@@ -334,6 +354,12 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         for (int k = 0; k < 2; ++k)
             if (f[k].end > f[k].begin) p.adj.push_back(f[k]);
     }
+    if (turn_ok && chunks.size() == 1 && !turn_items.empty()) {
+        LaunchRange r;
+        append(turn_items, 15, &r);
+        r.stream = p.cfg.stream ? 1 + KIND_TURN : 0;
+        p.turn.push_back(r);
+    }
     if (p.cfg.stream) {
         // 2^12-element tiles keep several workgroups per CU, which overlap
         // loads and work by themselves; only 2^15-element tiles prefetch
@@ -432,9 +458,10 @@ std::string describe_plan(const BuiltPlan &p)
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
-                  "\"exec\": %d, \"chunk\": %lld, \"stream\": %d, \"pipeline\": %d, \"order\": %d}, ",
+                  "\"exec\": %d, \"chunk\": %lld, \"stream\": %d, \"pipeline\": %d, \"order\": %d, "
+                  "\"turn\": %d}, ",
                   p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec,
-                  (long long)p.cfg.chunk, p.cfg.stream, p.cfg.pipeline, p.cfg.order);
+                  (long long)p.cfg.chunk, p.cfg.stream, p.cfg.pipeline, p.cfg.order, p.cfg.turn);
     s += buf;
     s += "\"splits\": [";
     for (size_t i = 0; i < p.splits.size(); ++i) {
@@ -460,6 +487,8 @@ std::string describe_plan(const BuiltPlan &p)
     ranges("forward", p.fwd);
     s += ", ";
     ranges("backward", p.adj);
+    s += ", ";
+    ranges("turn", p.turn);
     s += "}";
     return s;
 }

@@ -34,6 +34,9 @@ struct PlanConfig {
                         // intermediate is read back soon after it is written
     int order = 0;      // coefficient order (Order): set from the plan's
                         // flags, not a tuning choice
+    int turn = 1;       // 1: signed multi-round forward calls join round r's
+                        // last pass and round r + 1's first pass in one launch
+                        // of KIND_TURN tiles where the plan qualifies
     int stream = 1;     // 1: launches of full 2^15-element tiles of one kind
                         // run the prefetching kernel (a workgroup loops over
                         // items and fetches the next tile while the current
@@ -71,6 +74,12 @@ struct BuiltPlan {
     std::vector<int32_t> tiny_m;
     std::vector<LaunchRange> fwd;     // launches of a forward call, in order
     std::vector<LaunchRange> adj;     // launches of a backward call, in order
+    // round boundaries of signed multi-round forward calls: KIND_TURN items of
+    // every two-pass signal (2^15-element tiles); empty when the plan does not
+    // qualify (other orders, persistent or chunked launches, a dtype whose
+    // storage is narrower than its compute type, or a two-pass signal whose
+    // first pass is not in 2^15-element tiles)
+    std::vector<LaunchRange> turn;
     std::vector<Split> splits;        // distinct splits in use
     size_t ws_elems = 0;              // compact intermediate of this configuration
     size_t ws_bound = 0;              // intermediate bound over every configuration

@@ -28,6 +28,13 @@ enum ItemKind : int32_t {
     // workgroup.
     KIND_SIGNAL_A = 5,
     KIND_SIGNAL_B = 6,
+    // Round boundary of a signed multi-round call (forward, 2^15-element
+    // tiles): the last pass of round r on 2^(15-bits) consecutive blocks of the
+    // intermediate `inter`, then, on the same 2^15 output positions, round
+    // r + 1's diagonal and first pass (2^CC rows, CC = 15 - (m - bits)),
+    // stored transposed into `inter2`.  Fields as KIND_LAST, plus h0 (first
+    // row of the tile) and rs (= bits).
+    KIND_TURN = 7,
 };
 
 // Coefficient order of the transform's output (forward) / input (adjoint).
@@ -86,7 +93,8 @@ struct LaunchArgs {
     void *out;               // y
     void *inter;             // intermediate between passes (workspace or y)
     int32_t inter_is_io;     // 1: inter == y, offsets follow io_off
-    int32_t pad2;
+    int32_t inter2_is_io;    // KIND_TURN: 1 when inter2 == y
+    void *inter2;            // KIND_TURN: the next round's intermediate
     const Item *items;       // device array
     const int64_t *list;     // device array of block offsets (ragged BLOCKS)
     int32_t nitems;

@@ -130,7 +130,8 @@ def test_describe_and_planner_properties():
     # items: 2^L1 blocks of 2^(m - L1)
     rows_tiles = (1 << (20 - sp["L1"])) >> sp["rows_log2"]
     last_tiles = (1 << 20) >> sp["K2"]
-    assert plan["items"] == 3 * (rows_tiles + last_tiles)
+    # plus one round-boundary tile per 2^15 elements (signed multi-round calls)
+    assert plan["items"] == 3 * (rows_tiles + last_tiles + (1 << (20 - 15)))
     p.close()
 
 
@@ -472,3 +473,30 @@ def test_nodes_validation():
     assert lib.chw_nodes_forward(q.handle, x, y, w, -1, None) == 1
     assert lib.chw_nodes_forward(q.handle, ctypes.c_void_p(a + 2), y, w, 0, None) == 3
     assert lib.chw_nodes_forward(q.handle, x, x, w, 0, None) == 1
+
+
+def test_turn_plan_shape():
+    # round-boundary tiles: one 2^15-element tile per 2^15 elements of every
+    # two-pass signal, only where the plan qualifies
+    sizes = [16, 20, 21, 24, 26, 12, 3]
+    p = chw.Plan(sizes, dtype="f32")
+    p.check()
+    turn = p.describe()["plan"]["turn"]
+    assert len(turn) == 1 and turn[0]["K"] == 15 and turn[0]["stream"] == 8
+    assert turn[0]["end"] - turn[0]["begin"] == sum(1 << (k - 15) for k in sizes if k > 15)
+    q = chw.Plan(sizes, dtype="f32")
+    q.set_option("stream", 0)
+    q.check()
+    assert q.describe()["plan"]["turn"][0]["stream"] == 0
+    assert chw.Plan([20] * 2, dtype="i32", norm="none").describe()["plan"]["turn"]
+    for none in (chw.Plan([20] * 2, dtype="bf16"), chw.Plan([20] * 2, dtype="f64"),
+                 chw.Plan([20] * 2, dtype="f32", order="natural"),
+                 chw.Plan([20] * 2, dtype="f32", persistent=True),
+                 chw.Plan([12, 3], dtype="f32")):
+        none.check()
+        assert none.describe()["plan"]["turn"] == []
+    for key, val in (("turn", 0), ("chunk", 1 << 21), ("split_l1", 6)):
+        r = chw.Plan([20] * 4, dtype="f32")
+        r.set_option(key, val)
+        r.check()
+        assert r.describe()["plan"]["turn"] == [], key

@@ -215,3 +215,57 @@ def test_signed_persistent_and_split_forms(dtype):
     _sync()
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i32"])
+@pytest.mark.parametrize("mode", ["shared", "per_element"])
+def test_round_boundary_tiles_bitwise(dtype, mode):
+    # signed multi-round forward calls join round r's last pass and round
+    # r + 1's first pass (KIND_TURN tiles): the same bits as one launch pair per
+    # round, with and without prefetching, in place and out of place; every
+    # compiled first-pass row count (m = 16, 21: 2^7 rows; 24: 2^5; 26: 2^3)
+    t = gu.torch()
+    sizes = [16, 21, 12, 24, 3, 26, 20]
+    norm = "none" if dtype == "i32" else "ortho"
+    gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
+    x = np.concatenate([gen(760 + i, 1, k)[0] for i, k in enumerate(sizes)])
+    xd = gu.dev_tensor(x, dtype)
+    plans = {}
+    for turn, stream in ((0, 1), (1, 1), (1, 0)):
+        p = chw.Plan(sizes, dtype=dtype, norm=norm)
+        p.set_option("turn", turn)
+        p.set_option("stream", stream)
+        plans[(turn, stream)] = p
+    ref_plan = plans[(0, 1)]
+    assert ref_plan.describe()["plan"]["turn"] == []
+    assert plans[(1, 1)].describe()["plan"]["turn"]
+    nbits = (1 << max(sizes)) if mode == "shared" else ref_plan.extent
+    ws = t.empty(max(ref_plan.workspace_size(), 16), dtype=t.uint8, device="cuda")
+    for rounds in (2, 3, 4):
+        s = _signs_dev(workloads.pack_sign_bits(workloads.sign_rounds(770 + rounds, rounds, nbits)))
+        want = ref_plan.forward_signed(xd, s, mode, rounds, workspace=ws)
+        for key in ((1, 1), (1, 0)):
+            got = plans[key].forward_signed(xd, s, mode, rounds, workspace=ws)
+            inplace = xd.clone()
+            plans[key].forward_signed(inplace, s, mode, rounds, out=inplace, workspace=ws)
+            _sync()
+            assert t.equal(got, want), (rounds, key)
+            assert t.equal(inplace, want), (rounds, key, "in place")
+
+
+def test_round_boundary_tiles_against_oracle():
+    t = gu.torch()
+    sizes = [16, 20, 12]
+    rounds = 3
+    x = np.concatenate([workloads.float_signals(780 + i, 1, k)[0] for i, k in enumerate(sizes)])
+    p = chw.Plan(sizes, dtype="f32")
+    assert p.describe()["plan"]["turn"]
+    xd = gu.dev_tensor(x, "f32")
+    s = p.philox_signs(781, rounds, "per_element")
+    ws = t.empty(p.workspace_size(), dtype=t.uint8, device="cuda")
+    y = p.forward_signed(xd, s, "per_element", rounds, workspace=ws)
+    _sync()
+    from oracle import philox
+    diags = philox.diagonals(philox.sign_words(781, rounds, p.sign_words("per_element")), p.extent)
+    ref = signed.signed_batch(x.astype(np.float64), sizes, list(diags))
+    assert gu.per_signal_rel(gu.host_f64(y), ref, sizes).max() <= gu.TOL["f32"] * rounds
