@@ -270,8 +270,9 @@ def bench_forms(args, x, y, m, batch, stream):
     words = workloads.pack_sign_bits(workloads.sign_rounds(2002, k, 1 << m)).reshape(-1).view(np.int32)
     signs = torch.from_numpy(words.copy()).to(x.device)
     rec("signed_3_rounds", p, lambda: p.forward_signed(x, signs, "shared", k, out=y, workspace=ws),
-        "y = H D_3 H D_2 H D_1 x, one shared diagonal per round; two-pass signals run one "
-        "launch pair per round")
+        "y = H D_3 H D_2 H D_1 x, one shared diagonal per round; each round's last pass and "
+        "the next round's first pass run as one launch")
+    res["signed_3_rounds"]["launches_per_call"] = k + 1 if p.describe()["plan"]["turn"] else 2 * k
     # one round with a fresh per-element diagonal drawn on the device every call
     pe_words = torch.empty(p.sign_words("per_element"), dtype=torch.int32, device=x.device)
     seed = [0]
