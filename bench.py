@@ -463,8 +463,9 @@ def summarize(args):
     """
     trace_dir, fetch_dir, write_dir = args.summarize
     stats = _kernel_stats(trace_dir)
-    fetch = _counter(fetch_dir, "FETCH_SIZE")
-    write = _counter(write_dir, "WRITE_SIZE")
+    # "-" for FETCH and WRITE: a kernel-trace summary without counters
+    fetch = _counter(fetch_dir, "FETCH_SIZE") if fetch_dir != "-" else {}
+    write = _counter(write_dir, "WRITE_SIZE") if write_dir != "-" else {}
     copy_bytes = int(args.copy_gib * (1 << 30)) // 4 * 4
     copy_name = [k for k in fetch if "copyBuffer" in k]
     ff = fw = None
@@ -478,21 +479,25 @@ def summarize(args):
     traffic = None
     if ff and fw and args.calls:
         traffic = int((chw_fetch * ff + chw_write * fw) * 1024 / args.calls)
-    lines = ["# %s" % args.title, "",
-             "Kernel durations from `rocprofv3 --kernel-trace --stats` and HBM-side",
-             "bytes from two `rocprofv3 --pmc` runs (FETCH_SIZE, then WRITE_SIZE, KiB per",
-             "dispatch).  The counters are scaled by what they read for a plain",
-             "device-to-device copy of known size in the same run (%.2f GiB read and" % (copy_bytes / 2**30),
-             "written): fetch factor %s, write factor %s." % (
-                 "%.4f" % ff if ff else "n/a", "%.4f" % fw if fw else "n/a"), "",
-             "Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`):", ""]
+    if fetch:
+        head = ["Kernel durations from `rocprofv3 --kernel-trace --stats` and HBM-side",
+                "bytes from two `rocprofv3 --pmc` runs (FETCH_SIZE, then WRITE_SIZE, KiB per",
+                "dispatch).  The counters are scaled by what they read for a plain",
+                "device-to-device copy of known size in the same run (%.2f GiB read and" % (copy_bytes / 2**30),
+                "written): fetch factor %s, write factor %s." % (
+                    "%.4f" % ff if ff else "n/a", "%.4f" % fw if fw else "n/a")]
+    else:
+        head = ["Kernel durations from `rocprofv3 --kernel-trace --stats` (no counters)."]
+    lines = ["# %s" % args.title, ""] + head + [
+             "", "Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`):", ""]
     for c in args.cmd or []:
         lines.append("    " + c)
     lines += ["", "| kernel | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
     for k, v in stats.items():
         if "chw::" in k or "copyBuffer" in k:
             lines.append("| `%s` | %d | %.1f | %.1f | %.1f |" % (k[:90], len(v), sum(v) / len(v), min(v), max(v)))
-    lines += ["", "| kernel | dispatches | FETCH_SIZE KiB avg | WRITE_SIZE KiB avg |", "|---|---|---|---|"]
+    if fetch:
+        lines += ["", "| kernel | dispatches | FETCH_SIZE KiB avg | WRITE_SIZE KiB avg |", "|---|---|---|---|"]
     for k in fetch:
         if "chw::" in k or "copyBuffer" in k:
             lines.append("| `%s` | %d | %.0f | %.0f |" % (k[:90], len(fetch[k]), sum(fetch[k]) / len(fetch[k]),
