@@ -489,7 +489,8 @@ def summarize(args):
     else:
         head = ["Kernel durations from `rocprofv3 --kernel-trace --stats` (no counters)."]
     lines = ["# %s" % args.title, ""] + head + [
-             "", "Commands (from the repository root on the GPU box, after `cd /tmp && export TMPDIR=/tmp`):", ""]
+             "", "Commands (on the GPU machine, after `cd /tmp && export TMPDIR=/tmp`; REPO is the",
+             "repository root, P an output folder):", ""]
     for c in args.cmd or []:
         lines.append("    " + c)
     lines += ["", "| kernel | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
