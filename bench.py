@@ -56,9 +56,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(path, splits=None):
-    """Traffic per transform from a profiles/ summary, or None when the
-    summary was taken with other kernel sources or other pass splits."""
+def stored_profile(path, splits=None):
+    """The machine-readable summary of a profiles/ file, or None when it was
+    taken with other kernel sources or other pass splits."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -71,7 +71,13 @@ def stored_traffic(path, splits=None):
         return None
     if splits is not None and d.get("splits") is not None and d["splits"] != splits:
         return None
-    return d.get("traffic_bytes_per_transform")
+    return d
+
+
+def stored_traffic(path, splits=None):
+    """PMC bytes per transform from a profiles/ summary (None when stale)."""
+    d = stored_profile(path, splits)
+    return None if d is None else d.get("traffic_bytes_per_transform")
 
 
 def time_steps(fn, steps, warmup, stream):
@@ -101,25 +107,43 @@ def launch_breakdown(plan, fn, steps):
     return [] if acc is None else list(acc / steps)
 
 
-def roofline(elems, bytes_per_elem, launches_ms, kernel_names, traffic):
-    """Roofline of one transform: algorithmic bytes (bytes_per_elem per
-    element, one read and one write) over the transform's launch time."""
+def roofline(bytes_per_elem, launches_ms, launches, profile, total_elems):
+    """Roofline of the dominant kernel (the launch with the longest average
+    duration): its algorithmic bytes per launch -- bytes_per_elem (one read and
+    one write of an element at the storage type) times the elements the launch
+    takes through its part of the transform -- over its average duration;
+    `traffic` is the PMC bytes of one dispatch of that kernel.  `transform`
+    gives the same for the whole transform (all launches of one call, which
+    take total_elems elements through the whole transform)."""
     total_ms = float(sum(launches_ms))
-    algo = elems * bytes_per_elem
-    achieved = algo / (total_ms / 1e3) / 1e9
     dom = int(np.argmax(launches_ms)) if launches_ms else 0
-    # measured HBM fraction: the PMC bytes of every pass over the same time
-    measured = None if traffic is None else round(
-        traffic / (total_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    elems = int(total_elems)
+    if len(launches) != len(launches_ms):
+        # no per-launch timing: the call as one unit
+        launches = [{"name": "all launches of one call", "elements": elems, "symbol": None}
+                    for _ in launches_ms]
+    per_kernel = (profile or {}).get("kernels_traffic_bytes", {})
+    dom_l = launches[dom] if launches else {"name": None, "elements": 0, "symbol": None}
+    algo_dom = dom_l["elements"] * bytes_per_elem
+    achieved = algo_dom / (launches_ms[dom] / 1e3) / 1e9 if launches_ms else 0.0
+    t_traffic = None if profile is None else profile.get("traffic_bytes_per_transform")
+    t_achieved = elems * bytes_per_elem / (total_ms / 1e3) / 1e9 if total_ms else 0.0
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "measured_hbm_frac": measured,
-        "kernel": kernel_names[dom] if kernel_names else None,
-        "algorithmic_bytes_per_transform": algo,
-        "launches": [{"kernel": n, "ms": round(t, 4),
-                      "GBs_if_one_read_one_write": round(algo / (t / 1e3) / 1e9, 1)}
-                     for n, t in zip(kernel_names, launches_ms)],
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": per_kernel.get(dom_l["symbol"]) if profile else None,
+        "kernel": dom_l["name"],
+        "algorithmic_bytes_per_launch": algo_dom,
+        "units_per_launch": dom_l["elements"], "bytes_per_unit": bytes_per_elem,
+        "launches": [{"kernel": l["name"], "ms": round(t, 4), "elements": l["elements"],
+                      "GBs_algorithmic": round(l["elements"] * bytes_per_elem / (t / 1e3) / 1e9, 1)}
+                     for l, t in zip(launches, launches_ms)],
+        "transform": {
+            "achieved": round(t_achieved, 1), "frac": round(t_achieved / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes": elems * bytes_per_elem, "ms": round(total_ms, 4),
+            "traffic": t_traffic,
+            "measured_hbm_frac": None if t_traffic is None else round(
+                t_traffic / (total_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
 
 
@@ -137,21 +161,38 @@ def configure(plan, args, x, y, ws, key="plan"):
         plan.autotune(x, y, workspace=ws, iters=2)
 
 
-def launch_names(plan, direction="forward"):
+def plan_launches(plan, dt_code, direction="forward"):
+    """The launches of one call in order: a readable name, the kernel's symbol
+    as rocprofv3 prints it, and the elements the launch takes through its part
+    of the transform."""
     d = plan.describe()["plan"]
-    names = []
+    order = d["config"]["order"]
+    out = []
     if d["tiny"]:
-        names.append("chw_tiny_kernel")
-    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST", 5: "FIRST_C"}
+        out.append({"name": "chw_tiny_kernel", "elements": d["tiny_elements"], "symbol": None})
+    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST", 5: "FIRST_C", 8: "TURN"}
+    adj = "true" if direction == "backward" else "false"
     for r in d[direction]:
+        ca = 7 if r["K"] == 15 else 6
         if r["persistent"]:
-            kind = "chw_persistent_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])
+            name = "chw_persistent_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])
+            sym = "void chw::chw_persistent_kernel<%d, %d, %d, %d, 3, %s>(chw::LaunchArgs)" % (
+                dt_code, r["K"], r["LR"], ca, adj)
         elif r.get("stream"):
-            kind = "chw_stream_kernel<K=%d,LR=%d,%s>" % (r["K"], r["LR"], kinds[r["stream"]])
+            name = "chw_stream_kernel<K=%d,LR=%d,%s>" % (r["K"], r["LR"], kinds[r["stream"]])
+            sym = "void chw::chw_stream_kernel<%d, %d, %d, %d, 3, %s, %d>(chw::LaunchArgs)" % (
+                dt_code, r["K"], r["LR"], ca, adj, r["stream"] - 1)
         else:
-            kind = "chw_items_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])
-        names.append("%s items [%d,%d)" % (kind, r["begin"], r["end"]))
-    return names
+            name = "chw_items_kernel<K=%d,LR=%d>" % (r["K"], r["LR"])
+            sym = "void chw::chw_items_kernel<%d, %d, %d, %d, 3, %s, %d>(chw::LaunchArgs)" % (
+                dt_code, r["K"], r["LR"], ca, adj, order)
+        out.append({"name": "%s items [%d,%d)" % (name, r["begin"], r["end"]),
+                    "elements": r["elements"], "symbol": sym})
+    return out
+
+
+def launch_names(plan, direction="forward"):
+    return [l["name"] for l in plan_launches(plan, 0, direction)]
 
 
 def cpu_baseline(x_host, m, sample):
@@ -225,8 +266,8 @@ def bench_headline(args, dev, stream, out):
         "config": {"workload": "plain_2p20_f32: 1024 x 2^20 float32, orthonormal dyadic WHT",
                    "batch": batch, "log2_n": m, "plan": desc["config"],
                    "splits": desc["splits"], "autotuned": not args.no_tune},
-        "roofline": roofline(elems, 8, launches, names,
-                             stored_traffic(PROFILE_HEADLINE, desc["splits"])),
+        "roofline": roofline(8, launches, plan_launches(plan, 0),
+                             stored_profile(PROFILE_HEADLINE, desc["splits"]), elems),
         "parity": {"sampled_signals": idx, "max_rel_l2": rel},
         "forward_calls": calls,
     })
@@ -331,8 +372,8 @@ def bench_ragged_bf16(args, dev, stream):
            "ms_per_step": round(rms, 4), "signals": len(ks), "elements": relems,
            "dtype": "bf16 storage, fp32 compute", "plan": d["config"],
            "launches_per_call": len(d["forward"]),
-           "roofline": roofline(relems, 4, launches, launch_names(rp),
-                                stored_traffic(PROFILE_RAGGED, d["splits"])),
+           "roofline": roofline(4, launches, plan_launches(rp, 1),
+                                stored_profile(PROFILE_RAGGED, d["splits"]), relems),
            "parity": {"log2_sizes": [int(ks[i]) for i in sel], "max_rel_l2": max(rels)}}
     log("bf16 ragged: %.3f ms/step" % rms)
     del xb, yb, ws
@@ -394,12 +435,14 @@ def run_other(args, dev, stream):
     launches = launch_breakdown(plan, fn, args.steps) if not args.no_launch_timing else [ms]
     # algorithmic bytes: one read and one write of the data, plus the sign bits
     bpe = 2 * es + (k / 8.0 if k > 0 else 0.0)
-    names = launch_names(plan)
-    if k > 1:  # one set of launches per round
-        names = ["%s round %d" % (nm, r + 1) for r in range(k) for nm in names]
+    dt_code = {"f32": 0, "bf16": 1, "f16": 2, "i32": 3, "f64": 4}[plan.dtype]
+    ls = plan_launches(plan, dt_code)
+    if k > 1:  # several rounds: the launches of the call, in order
+        ls = [{"name": "launch %d of the call" % (i + 1), "elements": elems, "symbol": None}
+              for i in range(len(launches))]
     out = {"workload": w.name, "ms_per_step": round(ms, 4),
            "Gelem_s": round(elems / (ms / 1e3) / 1e9, 2),
-           "roofline": roofline(elems, bpe, launches, names, None),
+           "roofline": roofline(bpe, launches, ls, None, elems),
            "splits": plan.describe()["plan"]["splits"],
            "plan": plan.describe()["plan"]["config"],
            "forward_calls": args.warmup + args.steps * (1 if args.no_launch_timing else 2)}
@@ -508,9 +551,16 @@ def summarize(args):
         with open(args.bench_json) as f:
             bj = json.loads(f.read().strip().splitlines()[-1])
         splits = bj.get("config", {}).get("splits", bj.get("splits"))
+    per_kernel = {}
+    if ff and fw:
+        for k in fetch:
+            if "chw::" in k and write.get(k):
+                per_kernel[k[:90]] = int((sum(fetch[k]) / len(fetch[k]) * ff +
+                                          sum(write[k]) / len(write[k]) * fw) * 1024)
     summary = {"source_hash": kernel_source_hash(), "calls": args.calls, "splits": splits,
                "fetch_factor": ff, "write_factor": fw,
                "traffic_bytes_per_transform": traffic,
+               "kernels_traffic_bytes": per_kernel,
                "kernels_avg_us": {k[:90]: round(sum(v) / len(v), 2) for k, v in stats.items()
                                   if "chw::" in k}}
     lines += ["", "Machine-readable summary (the benchmark reports `traffic` from it while",

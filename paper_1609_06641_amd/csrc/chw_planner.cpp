@@ -450,11 +450,13 @@ std::string describe_plan(const BuiltPlan &p)
 {
     std::string s = "{";
     char buf[256];
+    int64_t tiny_elements = 0;
+    for (int32_t m : p.tiny_m) tiny_elements += (int64_t)1 << m;
     std::snprintf(buf, sizeof buf,
-                  "\"items\": %zu, \"list\": %zu, \"tiny\": %lld, \"single\": %lld, "
-                  "\"multi\": %lld, \"ws_elems\": %zu, ",
-                  p.items.size(), p.list.size(), (long long)p.n_tiny, (long long)p.n_single,
-                  (long long)p.n_multi, p.ws_elems);
+                  "\"items\": %zu, \"list\": %zu, \"tiny\": %lld, \"tiny_elements\": %lld, "
+                  "\"single\": %lld, \"multi\": %lld, \"ws_elems\": %zu, ",
+                  p.items.size(), p.list.size(), (long long)p.n_tiny, (long long)tiny_elements,
+                  (long long)p.n_single, (long long)p.n_multi, p.ws_elems);
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
@@ -471,6 +473,18 @@ std::string describe_plan(const BuiltPlan &p)
         s += buf;
     }
     s += "], ";
+    // elements a launch takes through its part of the transform: every
+    // element of its tiles (a whole-signal item counts its signal once)
+    auto elements = [&](const LaunchRange &r) {
+        int64_t n = 0;
+        for (int k = r.begin; k < r.end; ++k) {
+            const Item &it = p.items[k];
+            if (it.kind == KIND_BLOCKS || it.kind == KIND_LAST) n += (int64_t)it.count << it.bits;
+            else if (it.kind == KIND_SIGNAL_A || it.kind == KIND_SIGNAL_B) n += (int64_t)1 << it.m;
+            else n += (int64_t)1 << r.K;  // first-pass and round-boundary tiles
+        }
+        return n;
+    };
     auto ranges = [&](const char *name, const std::vector<LaunchRange> &v) {
         s += "\"";
         s += name;
@@ -478,8 +492,10 @@ std::string describe_plan(const BuiltPlan &p)
         for (size_t i = 0; i < v.size(); ++i) {
             const LaunchRange &r = v[i];
             std::snprintf(buf, sizeof buf,
-                          "%s{\"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d, \"persistent\": %d, \"stream\": %d}",
-                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent, r.stream);
+                          "%s{\"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d, \"persistent\": %d, "
+                          "\"stream\": %d, \"elements\": %lld}",
+                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent, r.stream,
+                          (long long)elements(r));
             s += buf;
         }
         s += "]";
