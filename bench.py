@@ -605,8 +605,8 @@ def main():
         summarize(args)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the batch shards across GPUs with no communication; see DESIGN.md)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(signals are independent, so a batch shards across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
 

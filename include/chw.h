@@ -68,7 +68,7 @@ typedef enum {
 typedef enum {
     CHW_OK = 0,
     CHW_ERR_INVALID_ARGUMENT = 1, /* NULL/negative/out-of-range/overlapping */
-    CHW_ERR_UNSUPPORTED = 2,      /* valid request this build cannot serve  */
+    CHW_ERR_UNSUPPORTED = 2,      /* valid request the library cannot serve */
     CHW_ERR_MISALIGNED = 3,       /* pointer or offset not 16-byte aligned  */
     CHW_ERR_OUT_OF_MEMORY = 4,    /* host/device allocation or size overflow */
     CHW_ERR_NO_DEVICE = 5,        /* no usable gfx950 device in this process */

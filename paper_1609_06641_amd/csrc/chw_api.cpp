@@ -939,7 +939,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     else if (k == "split_l1" && value >= -1 && value <= 30) cfg.split_l1 = (int)value;
     else if (k == "exec" && value == 1)
         return fail(CHW_ERR_UNSUPPORTED,
-                    "exec 1 (dependency-counter work queue) is disabled in this build");
+                    "exec 1 (dependency-counter work queue) is disabled");
     else if (k == "exec" && (value == 0 || value == 2)) cfg.exec = (int)value;
     else if (k == "chunk" && value >= 0) cfg.chunk = value;
     else if (k == "stream" && (value == 0 || value == 1)) cfg.stream = (int)value;

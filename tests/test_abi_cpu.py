@@ -59,7 +59,7 @@ def _plan_raw(sizes, offsets=None, dtype=0, norm=0, flags=0, batch=None):
     (dict(sizes=[10], flags=(1 << 2) | (1 << 3)), 1),  # exclusive flags
     (dict(sizes=[-1]), 1),
     (dict(sizes=[31]), 1),
-    (dict(sizes=[28]), 2),                             # beyond this build
+    (dict(sizes=[28]), 2),                             # beyond the largest supported size
     (dict(sizes=[21], dtype=4), 2),                    # F64 limit
     (dict(sizes=[4, 4], offsets=[0, 8, 24]), 1),       # overlap
     (dict(sizes=[4, 4], offsets=[0, 16, 20]), 1),      # end below last signal

@@ -1,0 +1,73 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the roofline
+record and the profile summaries it reads."""
+
+import json
+import subprocess
+import sys
+import os
+
+import pytest
+
+import bench
+from paper_1609_06641_amd import chw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def _fake_profile(symbols):
+    return {"traffic_bytes_per_transform": 3000, "kernels_traffic_bytes": {s: 1000 + i
+                                                                          for i, s in enumerate(symbols)}}
+
+
+def test_roofline_of_the_dominant_launch():
+    p = chw.Plan([20] * 4, dtype="f32")
+    p.set_option("split_l1", 8)
+    ls = bench.plan_launches(p, 0)
+    assert [l["elements"] for l in ls] == [4 << 20, 4 << 20]
+    assert ls[0]["symbol"].startswith("void chw::chw_stream_kernel<0, 15, 5, 7, 3, false, 1>")
+    prof = _fake_profile([l["symbol"] for l in ls])
+    r = bench.roofline(8, [2.0, 1.0], ls, prof, 4 << 20)
+    assert r["kernel"] == ls[0]["name"] and r["units_per_launch"] == 4 << 20
+    assert r["achieved"] == pytest.approx(8 * (4 << 20) / 2e-3 / 1e9, abs=0.06)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
+    assert r["traffic"] == 1000
+    t = r["transform"]
+    assert t["achieved"] == pytest.approx(8 * (4 << 20) / 3e-3 / 1e9, abs=0.06)
+    assert t["traffic"] == 3000
+    assert t["measured_hbm_frac"] == pytest.approx(3000 / 3e-3 / 1e9 / 8000.0, abs=1e-4)
+    # without per-launch timing the call counts as one unit
+    r1 = bench.roofline(8, [3.0], ls, prof, 4 << 20)
+    assert r1["traffic"] is None and r1["frac"] == t["frac"]
+
+
+def test_ragged_launch_elements_cover_the_batch():
+    import workloads
+    ks = workloads.ragged_log2_sizes(4001)
+    p = chw.Plan(ks, dtype="bf16")
+    ls = bench.plan_launches(p, 1)
+    two_pass = sum(1 << int(k) for k in ks if k > 15)
+    one_pass = sum(1 << int(k) for k in ks if k <= 15)
+    # every element once in a single-pass launch or once in each pass
+    assert sum(l["elements"] for l in ls) == one_pass + 2 * two_pass
+
+
+def test_profiles_name_their_kernels():
+    # the committed summaries carry per-kernel PMC bytes keyed by the symbols
+    # plan_launches derives
+    for path in (bench.PROFILE_HEADLINE, bench.PROFILE_RAGGED):
+        with open(path) as f:
+            text = f.read()
+        summary = json.loads(text.split("```json\n")[1].split("\n```")[0])
+        assert summary["kernels_traffic_bytes"]
+        for sym in summary["kernels_traffic_bytes"]:
+            assert sym.startswith("void chw::chw_")
+    p = chw.Plan([20] * 4, dtype="f32")
+    p.set_option("split_l1", 8)
+    with open(bench.PROFILE_HEADLINE) as f:
+        assert bench.plan_launches(p, 0)[0]["symbol"] in f.read()

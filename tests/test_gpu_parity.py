@@ -188,20 +188,20 @@ def test_split_invariance_bitwise():
                         for i, k in enumerate(sizes)])
     xd = gu.dev_tensor(x, "f32")
     outs = []
-    configs = [dict(), dict(lr12=5), dict(lr15=6), dict(single15=0),
+    cfgs = [dict(), dict(lr12=5), dict(lr15=6), dict(single15=0),
                dict(split_l1=9), dict(split_l1=6), dict(split_l1=12, lr15=6),
                dict(split_l1=8), dict(chunk=1 << 21), dict(exec=2), dict(exec=2, lr12=5),
                dict(stream=0), dict(stream=0, lr12=5), dict(stream=0, split_l1=12, lr15=6),
                dict(stream=0, split_l1=8, chunk=1 << 21), dict(stream=1, split_l1=6),
                dict(split_l1=10), dict(split_l1=10, stream=0),
                dict(chunk=1 << 20, pipeline=1), dict(chunk=1 << 19, pipeline=1, lr15=6)]
-    for cfg in configs:
+    for cfg in cfgs:
         p = chw.Plan(sizes, dtype="f32")
         for k, v in cfg.items():
             p.set_option(k, v)
         outs.append(gu.host_f64(p.forward(xd)))
     _sync()
-    for cfg, o in zip(configs[1:], outs[1:]):
+    for cfg, o in zip(cfgs[1:], outs[1:]):
         assert np.array_equal(o, outs[0]), cfg
     ref = gu.oracle_packed(x.astype(np.float64), sizes)
     assert gu.per_signal_rel(outs[0], ref, sizes).max() <= 1e-5
