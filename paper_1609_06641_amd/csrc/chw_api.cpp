@@ -246,8 +246,9 @@ chw_status mark(chw_plan_t p, DeviceState &ds, int i, hipStream_t stream)
 // run every round inside themselves, so they are enqueued with iteration 0
 // only; two-pass launches run one round each.  Timing events continue from
 // the call's previous ones unless `fresh`.
-// `phase` selects launches: 0 all; 1 the tiny kernel, single-pass and
-// first-pass launches; 2 the last-pass launches.
+// `phase` selects launches: 0 all; 1 the tiny kernel, single-pass launches
+// and the pass a two-pass signal starts with (forward: first pass; adjoint:
+// last pass); 2 the pass it ends with.
 chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
                    int inter_is_io, hipStream_t stream, const SignArgs &sg = SignArgs{},
                    int ri = 0, bool fresh = true, int phase = 0)
@@ -291,8 +292,9 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         const bool in_launch_rounds = fuse && (r.persistent || r.single_pass);
         if (in_launch_rounds && ri > 0) continue;
         if (phase != 0) {
-            const bool last = b.items[r.begin].kind == KIND_LAST;
-            if ((phase == 1) == last) continue;
+            const int kind = b.items[r.begin].kind;
+            const bool start = r.single_pass || (adj ? kind == KIND_LAST : is_first_kind(kind));
+            if ((phase == 1) != start) continue;
         }
         a.signs = in_launch_rounds ? sg.w : w_round;
         a.rounds = in_launch_rounds ? k : 1;
@@ -339,14 +341,15 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
 // The round-boundary launch between rounds ri - 1 and ri of a signed forward
 // call: KIND_TURN tiles read round ri - 1's intermediate `src` and write round
 // ri's intermediate `dst` (the workspace and y take turns).
-chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, void *src, int src_io, void *dst,
-                        int dst_io, void *y, hipStream_t stream, const SignArgs &sg, int ri)
+chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int src_io,
+                        void *dst, int dst_io, void *y, hipStream_t stream, const SignArgs &sg,
+                        int ri)
 {
     const BuiltPlan &b = p->built;
     int nev = p->timing ? ds.ev_used : 0;
     chw_status ms;
     for (const LaunchRange &r : b.turn) {
-        const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, 0);
+        const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
         if (!v || !v->launch_turn)
             return fail(CHW_ERR_UNSUPPORTED, "no round-boundary kernel for dtype %d, LR=%d", p->dt,
                         r.LR);
@@ -365,7 +368,7 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, void *src, int src_io, vo
         a.sign_words = (int64_t)sg.words;
         a.rounds = 1;
         hipError_t e;
-        if (r.stream) {
+        if (r.stream && v->launch_turn_stream) {
             int &cap = ds.grid_cap[v->fn_turn_stream];
             if (cap == 0) {
                 int per_cu = 0, dev = 0, cus = 0;
@@ -394,20 +397,31 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, void *src, int src_io, vo
 // whose plan has round-boundary tiles instead runs: the first pass of round
 // 0 (with the single-pass work), one round-boundary launch per later round,
 // and the last pass of the final round -- k + 1 passes over the two-pass
-// signals instead of 2k.
+// signals instead of 2k.  The adjoint does the same backwards: round k - 1's
+// adjoint last pass, boundaries that end round r and start round r - 1, and
+// round 0's adjoint first pass.
 chw_status enqueue_rounds(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y,
                           void *ws, void *inter0, int inter_is_io0, hipStream_t stream,
                           const SignArgs &sg)
 {
     const int k = sg.w ? sg.rounds : 1;
-    if (!adj && k > 1 && !p->built.turn.empty() && ws) {
-        // round i's intermediate: the workspace for even i, y for odd i
-        chw_status s = enqueue(p, ds, 0, x, y, ws, 0, stream, sg, 0, true, 1);
+    if (k > 1 && !p->built.turn.empty() && ws) {
+        // Intermediates 0 .. k-1 of the chain take turns between the workspace
+        // and y.  A pass that reads transposed runs from all over a signal
+        // must not write the buffer it reads: the forward's first pass reads x
+        // (which may be y), so its chain starts in the workspace and ends with
+        // the last pass in place on y; the adjoint's final first pass reads
+        // the last intermediate, so its chain ends in the workspace (its
+        // opening last pass, which reads and writes each tile's own range, may
+        // write y).
+        auto on_y = [&](int i) { return adj ? ((k - 1 - i) % 2 != 0) : (i % 2 != 0); };
+        auto buf = [&](int i) { return on_y(i) ? y : ws; };
+        chw_status s = enqueue(p, ds, adj, x, y, buf(0), on_y(0) ? 1 : 0, stream, sg, 0, true, 1);
         for (int i = 1; i < k && s == CHW_OK; ++i)
-            s = enqueue_turn(p, ds, (i - 1) % 2 ? y : ws, (i - 1) % 2, i % 2 ? y : ws, i % 2, y,
-                             stream, sg, i);
+            s = enqueue_turn(p, ds, adj, buf(i - 1), on_y(i - 1) ? 1 : 0, buf(i), on_y(i) ? 1 : 0,
+                             y, stream, sg, adj ? k - i : i);
         if (s != CHW_OK) return s;
-        return enqueue(p, ds, 0, y, y, (k - 1) % 2 ? y : ws, (k - 1) % 2, stream, sg, k - 1,
+        return enqueue(p, ds, adj, y, y, buf(k - 1), on_y(k - 1) ? 1 : 0, stream, sg, k - 1,
                        false, 2);
     }
     // later iterations have work when some launch runs one round at a time

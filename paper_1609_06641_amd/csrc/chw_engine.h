@@ -977,6 +977,74 @@ struct Engine {
         store_transp<CC, true>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
     }
 
+    // The adjoint's round boundary runs the other way: round r's adjoint
+    // first pass (transposed gather from the intermediate, stages L1 - 1 .. 0)
+    // leaves round r's output for 2^15 consecutive positions in natural order;
+    // turn_regather scales it, applies D_r and moves every position o to the
+    // tile element the last pass's Paley gather would have put it at, and the
+    // tile continues as round r - 1's adjoint last-pass tile (stages down to
+    // L1, contiguous store to the next intermediate).
+    static __device__ __forceinline__ void turn_regather(const Item &it, const LaunchArgs &a,
+                                                         C *lds, int t)
+    {
+        constexpr int V = Vec<C>::V, NV = N / (V * NT);
+        const int bits = it.bits;
+        const C sc = ortho_scale<C>(it.m);
+        const bool ortho = a.ortho != 0;
+        const C *rb = lds + L::pad(V * t);
+        C v[NV][V];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int u = 0; u < V; ++u) v[k][u] = rb[L::pad(V * NT * k) + u];
+        __syncthreads();
+        const SignCtx sg{a.signs, it.io_off - it.sig_off, a.sign_shared};
+        C *wb = lds + L::pad(brev_low(V * t, bits));
+        int ul[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) ul[u] = L::pad(brev_low(u, bits));
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int e0 = V * t + V * NT * k;
+            const uint32_t sb = sg.w ? sign_bits(sg, it.io_off + e0, e0) : 0u;
+            const int kl = L::pad(brev_low(V * NT * k, bits));
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                C x = v[k][u];
+                if (ortho) x = scale_mul(x, sc);
+                wb[kl + ul[u]] = apply_sign(x, (sb >> u) & 1u);
+            }
+        }
+        __syncthreads();
+    }
+
+    template <int CC>
+    static __device__ __forceinline__ void run_turn_adj_cc(const Item &it, const LaunchArgs &a,
+                                                           C *lds, int t)
+    {
+        const int64_t src = a.inter_is_io ? it.sig_off
+                                          : it.ws_off - ((int64_t)it.h0 << (K - CC));
+        load_transp<CC, true>(lds, static_cast<const C *>(a.inter), src, it.h0, it.rs, t);
+        __syncthreads();
+        rounds<true>(lds, K - CC, t);
+        turn_regather(it, a, lds, t);
+        rounds<true>(lds, it.bits, t);
+        store_contig<NT_INTER, C>(lds, static_cast<C *>(a.inter2),
+                                  a.inter2_is_io ? it.io_off : it.ws_off, it.bits, it.count,
+                                  nullptr, t, C(1), false);
+    }
+
+    static __device__ __forceinline__ void run_turn_adj(const Item &it, const LaunchArgs &a,
+                                                        C *lds, int t)
+    {
+        if constexpr (K >= 15) {
+            const int cc = K - (it.m - it.bits);
+            if (cc == CA) run_turn_adj_cc<CA>(it, a, lds, t);
+            else if (cc == CM) run_turn_adj_cc<CM>(it, a, lds, t);
+            else if (cc == CB) run_turn_adj_cc<CB>(it, a, lds, t);
+        }
+    }
+
     static __device__ __forceinline__ void finish_turn(const Item &it, const LaunchArgs &a,
                                                        C *lds, int t)
     {

@@ -27,8 +27,9 @@ struct ItemsVariant {
     const void *fn_stream[5];         // BLOCKS, FIRST_A, FIRST_B, LAST, FIRST_C
     ItemsLauncher launch_order[2];    // one workgroup per item, sequency and
                                       // natural coefficient order
-    ItemsLauncher launch_turn;        // KIND_TURN items (K = 15, forward), one
-    ItemsLauncher launch_turn_stream; // workgroup per item / prefetching
+    ItemsLauncher launch_turn;        // KIND_TURN items (K = 15), one workgroup
+                                      // per item (forward or adjoint boundary)
+    ItemsLauncher launch_turn_stream; // prefetching form (forward only)
     const void *fn_turn_stream;
 };
 

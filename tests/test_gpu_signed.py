@@ -220,10 +220,11 @@ def test_signed_persistent_and_split_forms(dtype):
 @pytest.mark.parametrize("dtype", ["f32", "i32"])
 @pytest.mark.parametrize("mode", ["shared", "per_element"])
 def test_round_boundary_tiles_bitwise(dtype, mode):
-    # signed multi-round forward calls join round r's last pass and round
-    # r + 1's first pass (KIND_TURN tiles): the same bits as one launch pair per
-    # round, with and without prefetching, in place and out of place; every
-    # compiled first-pass row count (m = 16, 21: 2^7 rows; 24: 2^5; 26: 2^3)
+    # signed multi-round calls join round r's last pass and round r + 1's
+    # first pass (KIND_TURN tiles; the adjoint the other way round): the same
+    # bits as one launch pair per round, with and without prefetching, in place
+    # and out of place; every compiled first-pass row count (m = 16, 21: 2^7
+    # rows; 24: 2^5; 26: 2^3)
     t = gu.torch()
     sizes = [16, 21, 12, 24, 3, 26, 20]
     norm = "none" if dtype == "i32" else "ortho"
@@ -244,13 +245,19 @@ def test_round_boundary_tiles_bitwise(dtype, mode):
     for rounds in (2, 3, 4):
         s = _signs_dev(workloads.pack_sign_bits(workloads.sign_rounds(770 + rounds, rounds, nbits)))
         want = ref_plan.forward_signed(xd, s, mode, rounds, workspace=ws)
+        want_b = ref_plan.backward_signed(xd, s, mode, rounds, workspace=ws)
         for key in ((1, 1), (1, 0)):
             got = plans[key].forward_signed(xd, s, mode, rounds, workspace=ws)
+            got_b = plans[key].backward_signed(xd, s, mode, rounds, workspace=ws)
             inplace = xd.clone()
             plans[key].forward_signed(inplace, s, mode, rounds, out=inplace, workspace=ws)
+            inplace_b = xd.clone()
+            plans[key].backward_signed(inplace_b, s, mode, rounds, out=inplace_b, workspace=ws)
             _sync()
             assert t.equal(got, want), (rounds, key)
             assert t.equal(inplace, want), (rounds, key, "in place")
+            assert t.equal(got_b, want_b), (rounds, key, "adjoint")
+            assert t.equal(inplace_b, want_b), (rounds, key, "adjoint in place")
 
 
 def test_round_boundary_tiles_against_oracle():
@@ -264,8 +271,11 @@ def test_round_boundary_tiles_against_oracle():
     s = p.philox_signs(781, rounds, "per_element")
     ws = t.empty(p.workspace_size(), dtype=t.uint8, device="cuda")
     y = p.forward_signed(xd, s, "per_element", rounds, workspace=ws)
+    g = p.backward_signed(xd, s, "per_element", rounds, workspace=ws)
     _sync()
     from oracle import philox
     diags = philox.diagonals(philox.sign_words(781, rounds, p.sign_words("per_element")), p.extent)
     ref = signed.signed_batch(x.astype(np.float64), sizes, list(diags))
     assert gu.per_signal_rel(gu.host_f64(y), ref, sizes).max() <= gu.TOL["f32"] * rounds
+    ref_g = signed.signed_batch(x.astype(np.float64), sizes, list(diags), adjoint=True)
+    assert gu.per_signal_rel(gu.host_f64(g), ref_g, sizes).max() <= gu.TOL["f32"] * rounds
