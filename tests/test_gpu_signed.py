@@ -153,13 +153,17 @@ def test_signed_graph_replay():
     sB = _signs_dev(workloads.pack_sign_bits(workloads.sign_rounds(732, 2, 1 << 16)))
     wantA = pe.forward_signed(xd, sA, "shared", 2, workspace=ws)
     wantB = pe.forward_signed(xd, sB, "shared", 2, workspace=ws)
+    backA = pe.backward_signed(xd, sA, "shared", 2, workspace=ws)
     _sync()
-    yA, yB = t.empty_like(xd), t.empty_like(xd)
+    # the two-pass signals join their round boundaries (forward and adjoint)
+    assert pg.describe()["plan"]["turn"]
+    yA, yB, gA = t.empty_like(xd), t.empty_like(xd), t.empty_like(xd)
     for _ in range(3):
         pg.forward_signed(xd, sA, "shared", 2, out=yA, workspace=ws)
         pg.forward_signed(xd, sB, "shared", 2, out=yB, workspace=ws)
+        pg.backward_signed(xd, sA, "shared", 2, out=gA, workspace=ws)
         _sync()
-        assert t.equal(yA, wantA) and t.equal(yB, wantB)
+        assert t.equal(yA, wantA) and t.equal(yB, wantB) and t.equal(gA, backA)
     assert not t.equal(wantA, wantB)
 
 
