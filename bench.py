@@ -505,7 +505,7 @@ def summarize(args):
     transform; --calls is the number of transforms each PMC run made.
     """
     trace_dir, fetch_dir, write_dir = args.summarize
-    stats = _kernel_stats(trace_dir)
+    stats = _kernel_stats(trace_dir) if trace_dir != "-" else {}
     # "-" for FETCH and WRITE: a kernel-trace summary without counters
     fetch = _counter(fetch_dir, "FETCH_SIZE") if fetch_dir != "-" else {}
     write = _counter(write_dir, "WRITE_SIZE") if write_dir != "-" else {}
@@ -522,7 +522,9 @@ def summarize(args):
     traffic = None
     if ff and fw and args.calls:
         traffic = int((chw_fetch * ff + chw_write * fw) * 1024 / args.calls)
-    if fetch:
+    if not stats:
+        head = ["Counters from `rocprofv3 --pmc` (per dispatch, averaged over the dispatches)."]
+    elif fetch:
         head = ["Kernel durations from `rocprofv3 --kernel-trace --stats` and HBM-side",
                 "bytes from two `rocprofv3 --pmc` runs (FETCH_SIZE, then WRITE_SIZE, KiB per",
                 "dispatch).  The counters are scaled by what they read for a plain",
@@ -536,7 +538,8 @@ def summarize(args):
              "repository root, P an output folder):", ""]
     for c in args.cmd or []:
         lines.append("    " + c)
-    lines += ["", "| kernel | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
+    if stats:
+        lines += ["", "| kernel | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
     for k, v in stats.items():
         if "chw::" in k or "copyBuffer" in k:
             lines.append("| `%s` | %d | %.1f | %.1f | %.1f |" % (k[:90], len(v), sum(v) / len(v), min(v), max(v)))
@@ -546,6 +549,24 @@ def summarize(args):
         if "chw::" in k or "copyBuffer" in k:
             lines.append("| `%s` | %d | %.0f | %.0f |" % (k[:90], len(fetch[k]), sum(fetch[k]) / len(fetch[k]),
                                                          sum(write.get(k, [0])) / max(1, len(write.get(k, [0])))))
+    counters = {}
+    if args.counters:
+        con = _db(args.counters)
+        rows = con.execute("select kernel_name, counter_name, avg(value), count(*) from "
+                           "counters_collection group by kernel_name, counter_name").fetchall()
+        for k, c, v, n in rows:
+            if "chw::" in k:
+                counters.setdefault(k[:90], {})[c] = v
+        names = sorted({c for d in counters.values() for c in d})
+        lines += ["", "| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+        for k, d in counters.items():
+            lines.append("| `%s` | " % k + " | ".join("%.0f" % d.get(c, float("nan")) for c in names) + " |")
+        if all(c in names for c in ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE")):
+            lines += ["", "Bank-conflict cycles per conflict-free LDS cycle "
+                      "(SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)):", ""]
+            for k, d in counters.items():
+                act, bc = d["SQ_LDS_IDX_ACTIVE"], d["SQ_LDS_BANK_CONFLICT"]
+                lines.append("* `%s`: %.3f" % (k, bc / max(1.0, act - bc)))
     splits = None
     if args.bench_json and os.path.exists(args.bench_json):
         with open(args.bench_json) as f:
@@ -563,6 +584,8 @@ def summarize(args):
                "kernels_traffic_bytes": per_kernel,
                "kernels_avg_us": {k[:90]: round(sum(v) / len(v), 2) for k, v in stats.items()
                                   if "chw::" in k}}
+    if counters:
+        summary["counters"] = counters
     lines += ["", "Machine-readable summary (the benchmark reports `traffic` from it while",
               "`source_hash` matches the kernel sources):", "", "```json",
               json.dumps(summary, indent=1), "```", ""]
@@ -595,6 +618,8 @@ def main():
                     help="also time a plain device copy of this many GiB (calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--calls", type=int, default=0)
+    ap.add_argument("--counters", help="with --summarize: a rocprofv3 --pmc output folder whose "
+                                       "counters are tabulated per kernel")
     ap.add_argument("--title", default="profile")
     ap.add_argument("--cmd", action="append")
     ap.add_argument("--out")
