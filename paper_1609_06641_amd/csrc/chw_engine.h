@@ -934,6 +934,11 @@ struct Engine {
         return r;
     }
 
+    //
+    // Register i of thread t holds tile element brev_low(o0 + i, bits): its
+    // register bits b are tile bits bits - 1 - b, so the last LR stages of
+    // round r (tile bits bits - LR .. bits - 1, in that order) run here too,
+    // on register bits LR - 1 .. 0, before the scale and the diagonal.
     static __device__ __forceinline__ void turn_round0(const Item &it, const LaunchArgs &a,
                                                        int nst, C *lds, int t)
     {
@@ -944,6 +949,8 @@ struct Engine {
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = lds[rb + L::pad(brev_low(i, bits))];
         __syncthreads();
+#pragma unroll
+        for (int b = LR - 1; b >= 0; --b) bfly(v, b);
         const C sc = ortho_scale<C>(it.m);
         const bool ortho = a.ortho != 0;
         const uint64_t sb = a.signs ? sign_window(a.signs, a.sign_shared ? it.io_off - it.sig_off + o0
@@ -969,7 +976,7 @@ struct Engine {
                                                           C *lds, int t)
     {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
-        rounds<false>(lds, it.bits, t);
+        rounds<false>(lds, it.bits - LR, t);  // round r's stages below the last LR
         turn_round0(it, a, K - CC, lds, t);
         rounds<false, 1>(lds, K - CC, t);
         const int64_t base = a.inter2_is_io ? it.sig_off
@@ -980,41 +987,55 @@ struct Engine {
     // The adjoint's round boundary runs the other way: round r's adjoint
     // first pass (transposed gather from the intermediate, stages L1 - 1 .. 0)
     // leaves round r's output for 2^15 consecutive positions in natural order;
-    // turn_regather scales it, applies D_r and moves every position o to the
-    // tile element the last pass's Paley gather would have put it at, and the
-    // tile continues as round r - 1's adjoint last-pass tile (stages down to
-    // L1, contiguous store to the next intermediate).
-    static __device__ __forceinline__ void turn_regather(const Item &it, const LaunchArgs &a,
-                                                         C *lds, int t)
+    // scaled and multiplied by D_r, it moves to the tile elements the last
+    // pass's Paley gather would have put it at, and the tile continues as
+    // round r - 1's adjoint last-pass tile (stages down to L1, contiguous store
+    // to the next intermediate).
+    // Register rounds J - 1 .. 1 of an adjoint pass (register round 0, tile
+    // bits 0 .. LR - 1, left out).
+    template <int j>
+    static __device__ __forceinline__ void rounds_down_to1(C *lds, int nst, int t)
     {
-        constexpr int V = Vec<C>::V, NV = N / (V * NT);
+        if constexpr (j >= 1) {
+            round<j, true>(lds, nst, t);
+            rounds_down_to1<j - 1>(lds, nst, t);
+        }
+    }
+
+    // The middle of the adjoint's round boundary in one register round: thread
+    // t takes the 2^LR consecutive positions of register round 0, runs round
+    // r's last adjoint first-pass stages (tile bits LR - 1 .. 0), scales and
+    // applies D_r, runs round r - 1's first adjoint last-pass stages (tile bits
+    // bits - 1 .. bits - LR of the Paley-gathered tile, which are register bits
+    // 0 .. LR - 1) and writes the values at their Paley-gathered places.
+    static __device__ __forceinline__ void turn_round_adj(const Item &it, const LaunchArgs &a,
+                                                          C *lds, int t)
+    {
         const int bits = it.bits;
+        const int o0 = t << LR;
+        const C *nb = lds + L::pad(o0);
+        C v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = nb[L::pad(i)];
+        __syncthreads();
+#pragma unroll
+        for (int b = LR - 1; b >= 0; --b) bfly(v, b);
         const C sc = ortho_scale<C>(it.m);
         const bool ortho = a.ortho != 0;
-        const C *rb = lds + L::pad(V * t);
-        C v[NV][V];
+        const uint64_t sb = a.signs ? sign_window(a.signs, a.sign_shared ? it.io_off - it.sig_off + o0
+                                                                         : it.io_off + o0, R)
+                                    : 0ull;
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-#pragma unroll
-            for (int u = 0; u < V; ++u) v[k][u] = rb[L::pad(V * NT * k) + u];
-        __syncthreads();
-        const SignCtx sg{a.signs, it.io_off - it.sig_off, a.sign_shared};
-        C *wb = lds + L::pad(brev_low(V * t, bits));
-        int ul[V];
-#pragma unroll
-        for (int u = 0; u < V; ++u) ul[u] = L::pad(brev_low(u, bits));
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const int e0 = V * t + V * NT * k;
-            const uint32_t sb = sg.w ? sign_bits(sg, it.io_off + e0, e0) : 0u;
-            const int kl = L::pad(brev_low(V * NT * k, bits));
-#pragma unroll
-            for (int u = 0; u < V; ++u) {
-                C x = v[k][u];
-                if (ortho) x = scale_mul(x, sc);
-                wb[kl + ul[u]] = apply_sign(x, (sb >> u) & 1u);
-            }
+        for (int i = 0; i < R; ++i) {
+            C x = v[i];
+            if (ortho) x = scale_mul(x, sc);
+            v[i] = apply_sign(x, (uint32_t)(sb >> i) & 1u);
         }
+#pragma unroll
+        for (int b = 0; b < LR; ++b) bfly(v, b);
+        C *wb = lds + L::pad(brev_low(o0, bits));
+#pragma unroll
+        for (int i = 0; i < R; ++i) wb[L::pad(brev_low(i, bits))] = v[i];
         __syncthreads();
     }
 
@@ -1022,13 +1043,14 @@ struct Engine {
     static __device__ __forceinline__ void run_turn_adj_cc(const Item &it, const LaunchArgs &a,
                                                            C *lds, int t)
     {
+        static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
         const int64_t src = a.inter_is_io ? it.sig_off
                                           : it.ws_off - ((int64_t)it.h0 << (K - CC));
         load_transp<CC, true>(lds, static_cast<const C *>(a.inter), src, it.h0, it.rs, t);
         __syncthreads();
-        rounds<true>(lds, K - CC, t);
-        turn_regather(it, a, lds, t);
-        rounds<true>(lds, it.bits, t);
+        rounds_down_to1<J - 1>(lds, K - CC, t);  // round r: stages L1 - 1 .. LR
+        turn_round_adj(it, a, lds, t);
+        rounds<true>(lds, it.bits - LR, t);      // round r - 1: stages bits - LR - 1 .. 0
         store_contig<NT_INTER, C>(lds, static_cast<C *>(a.inter2),
                                   a.inter2_is_io ? it.io_off : it.ws_off, it.bits, it.count,
                                   nullptr, t, C(1), false);

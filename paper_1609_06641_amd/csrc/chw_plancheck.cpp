@@ -125,7 +125,8 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             for (int k = r.begin; k < r.end; ++k) {
                 const Item &it = p.items[k];
                 const int L1 = it.m - it.bits, cc = 15 - L1;
-                if (it.kind != KIND_TURN || ((int64_t)it.count << it.bits) != ((int64_t)1 << 15) ||
+                if (it.kind != KIND_TURN || it.bits < 8 ||
+                    ((int64_t)it.count << it.bits) != ((int64_t)1 << 15) ||
                     (cc != K15_CA && cc != K15_CM && cc != K15_CB) || it.rs != it.bits ||
                     ((it.io_off - it.sig_off) & 32767) != 0 ||
                     (int64_t)it.h0 != ((it.io_off - it.sig_off) >> L1)) {

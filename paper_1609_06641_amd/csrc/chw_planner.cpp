@@ -208,8 +208,10 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             ch.last[kidx(sp.K2)].push_back(it);
         }
         // round boundary tiles: 2^15 consecutive positions = 2^CC first-pass
-        // rows of the next round (first pass in 2^15-element tiles only)
-        if (sp.K1 != 15) turn_ok = false;
+        // rows of the next round (first pass in 2^15-element tiles only, and
+        // last-pass blocks of at least 2^8, which the tile's first register
+        // round needs)
+        if (sp.K1 != 15 || b < 8) turn_ok = false;
         if (turn_ok) {
             for (int64_t tl = 0; tl < ((int64_t)1 << (m - 15)); ++tl) {
                 Item it = blank_item();

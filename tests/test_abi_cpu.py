@@ -495,6 +495,12 @@ def test_turn_plan_shape():
                  chw.Plan([12, 3], dtype="f32")):
         none.check()
         assert none.describe()["plan"]["turn"] == []
+    # forced splits whose last-pass blocks are below 2^8 take no round-boundary tiles
+    f = chw.Plan([16] * 4, dtype="f32")
+    f.set_option("split_l1", 12)
+    f.check()
+    assert f.describe()["plan"]["splits"][0]["L1"] == 12
+    assert f.describe()["plan"]["turn"] == []
     for key, val in (("turn", 0), ("chunk", 1 << 21), ("split_l1", 6)):
         r = chw.Plan([20] * 4, dtype="f32")
         r.set_option(key, val)
