@@ -346,7 +346,9 @@ chw_status chw_launch_times(chw_plan_t plan, float *ms, int *n);
  * covered exactly once per pass (one single-pass tile, or one first-pass and
  * one last-pass tile), no tile leaves its signal or the workspace, launches of
  * the two passes are ordered, persistent whole-signal items fit the tile
- * sizes, and prefetching launches hold only full tiles of one kind.  CHW_OK, or
+ * sizes, prefetching launches hold only full tiles of one kind, and the
+ * round-boundary tiles of signed multi-round calls cover every two-pass
+ * signal exactly once.  CHW_OK, or
  * CHW_ERR_UNSUPPORTED with the reason in chw_last_error(). */
 chw_status chw_plan_check(chw_plan_t plan);
 
@@ -356,8 +358,10 @@ chw_status chw_plan_describe(chw_plan_t plan, char *buf, size_t len);
 
 /* Time the candidate configurations of this plan on the given buffers (y and
  * workspace are overwritten; x is read only unless x == y) and keep the
- * fastest.  `iters` timed repetitions per candidate.  Every candidate
- * computes bitwise-identical results. */
+ * fastest.  `iters` timed repetitions per candidate.  The plan's own
+ * configuration is timed first, and another replaces the best so far only
+ * when it is more than 1% faster.  Every candidate computes
+ * bitwise-identical results. */
 chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace,
                         void *stream, int iters);
 

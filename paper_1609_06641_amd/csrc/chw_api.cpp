@@ -1075,6 +1075,10 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             if (plan->dt == DT_F64 && lr12 != 5) continue;
             cands.push_back(c);
         }
+    // the plan's own configuration first: another one replaces the best so far
+    // only when it is more than 1% faster, so near-ties keep the default and
+    // repeated tunings pick the same kernels
+    cands.insert(cands.begin(), plan->cfg);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(CHW_ERR_HIP, "hipEventCreate failed");
@@ -1100,7 +1104,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
         if (log_enabled())
             std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d stream=%d chunk=%lld pipeline=%d: %.4f ms\n",
                          c.exec, c.lr12, c.lr15, c.single15, c.split_l1, c.stream, (long long)c.chunk, c.pipeline, ms / iters);
-        if (ms < best_ms) {
+        if (ms < 0.99f * best_ms) {
             best_ms = ms;
             best = c;
         }
