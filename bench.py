@@ -408,7 +408,7 @@ def run_other(args, dev, stream):
     x = xv.reshape(-1).to(tdt).to(dev)
     y = torch.empty_like(x)
     ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device=dev)
-    configure(plan, args, x, y, ws)
+    configure(plan, args, x, y, ws, key="ragged" if w.name.startswith("ragged") else "plan")
     es = x.element_size()
     k = args.signed_rounds
     if k > 0:
