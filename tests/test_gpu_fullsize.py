@@ -5,6 +5,7 @@ hold for every signal (Parseval, the DC term, involution)."""
 import numpy as np
 import pytest
 
+import bench
 import workloads
 from oracle import metrics
 from paper_1609_06641_amd import chw
@@ -39,10 +40,10 @@ def test_plain_2p20_f32_bench_config():
     m, b = 20, w.batch
     xh = workloads.float_signals(w.seed, b, m)
     x = torch.from_numpy(xh).cuda()
-    plan = chw.Plan([m] * b, dtype="f32")
-    y = torch.empty_like(x)
-    plan.autotune(x, y, iters=2)                # the configuration the bench times
-    y = plan.forward(x, out=y)
+    plan = chw.Plan([m] * b, dtype="f32")       # the configuration the bench times
+    for k, v in bench.BENCH_CONFIG["plan"].items():
+        plan.set_option(k, v)
+    y = plan.forward(x)
     torch.cuda.synchronize()
     idx = [0, 1, 517, b - 2, b - 1] + list(np.random.default_rng(7).integers(0, b, 3))
     ref = gu.oracle_packed(xh[idx].astype(np.float64).reshape(-1), [m] * len(idx), threads=16)
@@ -97,8 +98,9 @@ def test_ragged_full(dtype, persistent):
     plan = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=persistent)
     ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device="cuda")
     if dtype == "bf16" and persistent:
-        # the bench's ragged form: persistent graph plan, then autotuned
-        plan.autotune(xt, torch.empty_like(xt), workspace=ws, iters=2)
+        # the bench's ragged form: a persistent graph plan set to its options
+        for k, v in bench.BENCH_CONFIG["ragged"].items():
+            plan.set_option(k, v)
     y = plan.forward(xt, workspace=ws)
     torch.cuda.synchronize()
     # every signal with m <= 12 against the oracle, plus 40 large ones
