@@ -368,20 +368,38 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int s
         a.sign_words = (int64_t)sg.words;
         a.rounds = 1;
         hipError_t e;
-        if (r.stream && v->launch_turn_stream) {
-            int &cap = ds.grid_cap[v->fn_turn_stream];
+        // prefetching form: the forward's handles every row count; the adjoint's
+        // is compiled per row count (the launch's items share one)
+        ItemsLauncher sl = nullptr;
+        const void *sfn = nullptr;
+        if (r.stream) {
+            if (!adj) {
+                sl = v->launch_turn_stream;
+                sfn = v->fn_turn_stream;
+            } else {
+                const Item &f = b.items[r.begin];
+                const int cc = 15 - (f.m - f.bits);
+                const int i = cc == K15_CA ? 0 : cc == K15_CM ? 1 : cc == K15_CB ? 2 : -1;
+                if (i >= 0) {
+                    sl = v->launch_turn_adj_stream[i];
+                    sfn = v->fn_turn_adj_stream[i];
+                }
+            }
+        }
+        if (sl && sfn) {
+            int &cap = ds.grid_cap[sfn];
             if (cap == 0) {
                 int per_cu = 0, dev = 0, cus = 0;
                 (void)hipGetDevice(&dev);
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v->fn_turn_stream, v->nt,
-                                                                 0) != hipSuccess || per_cu < 1) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sfn, v->nt, 0) != hipSuccess ||
+                    per_cu < 1) {
                     (void)hipGetLastError();
                     per_cu = 1;
                 }
                 (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
                 cap = per_cu * std::max(1, cus);
             }
-            e = v->launch_turn_stream(dim3(std::min(a.nitems, cap)), stream, a);
+            e = sl(dim3(std::min(a.nitems, cap)), stream, a);
         } else {
             e = v->launch_turn(dim3(a.nitems), stream, a);
         }

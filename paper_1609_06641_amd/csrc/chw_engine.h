@@ -1039,15 +1039,29 @@ struct Engine {
         __syncthreads();
     }
 
+    // signal base of the intermediate the adjoint boundary gathers from
+    template <int CC>
+    static __device__ __forceinline__ int64_t turn_adj_src(const Item &it, const LaunchArgs &a)
+    {
+        return a.inter_is_io ? it.sig_off : it.ws_off - ((int64_t)it.h0 << (K - CC));
+    }
+
     template <int CC>
     static __device__ __forceinline__ void run_turn_adj_cc(const Item &it, const LaunchArgs &a,
                                                            C *lds, int t)
     {
-        static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
-        const int64_t src = a.inter_is_io ? it.sig_off
-                                          : it.ws_off - ((int64_t)it.h0 << (K - CC));
-        load_transp<CC, true>(lds, static_cast<const C *>(a.inter), src, it.h0, it.rs, t);
+        load_transp<CC, true>(lds, static_cast<const C *>(a.inter), turn_adj_src<CC>(it, a),
+                              it.h0, it.rs, t);
         __syncthreads();
+        finish_turn_adj<CC>(it, a, lds, t);
+    }
+
+    // the adjoint boundary after its transposed gather
+    template <int CC>
+    static __device__ __forceinline__ void finish_turn_adj(const Item &it, const LaunchArgs &a,
+                                                           C *lds, int t)
+    {
+        static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
         rounds_down_to1<J - 1>(lds, K - CC, t);  // round r: stages L1 - 1 .. LR
         turn_round_adj(it, a, lds, t);
         rounds<true>(lds, it.bits - LR, t);      // round r - 1: stages bits - LR - 1 .. 0

@@ -125,6 +125,11 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             for (int k = r.begin; k < r.end; ++k) {
                 const Item &it = p.items[k];
                 const int L1 = it.m - it.bits, cc = 15 - L1;
+                const Item &first = p.items[r.begin];
+                if (L1 != first.m - first.bits) {
+                    *err = "round-boundary launch mixes first-pass row counts";
+                    return false;
+                }
                 if (it.kind != KIND_TURN || it.bits < 8 ||
                     ((int64_t)it.count << it.bits) != ((int64_t)1 << 15) ||
                     (cc != K15_CA && cc != K15_CM && cc != K15_CB) || it.rs != it.bits ||

@@ -357,10 +357,18 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             if (f[k].end > f[k].begin) p.adj.push_back(f[k]);
     }
     if (turn_ok && chunks.size() == 1 && !turn_items.empty()) {
-        LaunchRange r;
-        append(turn_items, 15, &r);
-        r.stream = p.cfg.stream ? 1 + KIND_TURN : 0;
-        p.turn.push_back(r);
+        // one launch per first-pass row count (the adjoint's prefetching form is
+        // compiled per row count)
+        for (int cc : {K15_CA, K15_CM, K15_CB}) {
+            std::vector<Item> v;
+            for (const Item &it : turn_items)
+                if (15 - (it.m - it.bits) == cc) v.push_back(it);
+            if (v.empty()) continue;
+            LaunchRange r;
+            append(v, 15, &r);
+            r.stream = p.cfg.stream ? 1 + KIND_TURN : 0;
+            p.turn.push_back(r);
+        }
     }
     if (p.cfg.stream) {
         // 2^12-element tiles keep several workgroups per CU, which overlap

@@ -29,8 +29,10 @@ struct ItemsVariant {
                                       // natural coefficient order
     ItemsLauncher launch_turn;        // KIND_TURN items (K = 15), one workgroup
                                       // per item (forward or adjoint boundary)
-    ItemsLauncher launch_turn_stream; // prefetching form (forward only)
+    ItemsLauncher launch_turn_stream; // prefetching form (forward)
     const void *fn_turn_stream;
+    ItemsLauncher launch_turn_adj_stream[3];  // prefetching adjoint form per
+    const void *fn_turn_adj_stream[3];        // row count: 2^CA, 2^CM, 2^CB
 };
 
 struct TinyVariant {

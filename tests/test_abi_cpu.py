@@ -482,12 +482,14 @@ def test_turn_plan_shape():
     p = chw.Plan(sizes, dtype="f32")
     p.check()
     turn = p.describe()["plan"]["turn"]
-    assert len(turn) == 1 and turn[0]["K"] == 15 and turn[0]["stream"] == 8
-    assert turn[0]["end"] - turn[0]["begin"] == sum(1 << (k - 15) for k in sizes if k > 15)
+    # one launch per first-pass row count: 2^7 rows (m = 16, 20, 21), 2^5 (24), 2^3 (26)
+    assert len(turn) == 3 and all(r["K"] == 15 and r["stream"] == 8 for r in turn)
+    assert sum(r["end"] - r["begin"] for r in turn) == sum(1 << (k - 15) for k in sizes if k > 15)
+    assert [r["end"] - r["begin"] for r in turn] == [2 + 32 + 64, 512, 2048]
     q = chw.Plan(sizes, dtype="f32")
     q.set_option("stream", 0)
     q.check()
-    assert q.describe()["plan"]["turn"][0]["stream"] == 0
+    assert all(r["stream"] == 0 for r in q.describe()["plan"]["turn"])
     assert chw.Plan([20] * 2, dtype="i32", norm="none").describe()["plan"]["turn"]
     for none in (chw.Plan([20] * 2, dtype="bf16"), chw.Plan([20] * 2, dtype="f64"),
                  chw.Plan([20] * 2, dtype="f32", order="natural"),
