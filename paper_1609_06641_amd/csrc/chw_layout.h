@@ -6,10 +6,12 @@
 // "round" a thread holds R = 2^LR elements in registers.
 //
 // The two padding shifts and the lane order of the transposed phase were
-// chosen with a model of the LDS banks (one 64-lane wave on 64 banks, and
-// half-waves on 32 banks): with them no phase of a compiled tile puts more
-// than two distinct words of one wave access into one bank (the self-check
-// reports the figures for every phase).
+// chosen with the bank rule measured on gfx950 for 4-byte LDS accesses: 32
+// banks (word address mod 32), each half-wave (lanes 0-31, 32-63) served on
+// its own.  With one word of padding every 2^5 and every 2^10 elements, no
+// half-wave access of any phase of a compiled FP32 / int32 tile (register
+// rounds, contiguous, Paley, transposed) puts two distinct words into one bank
+// (the self-check reports the figures for every phase).
 //
 // Stage t of the cascade is the set of Haar levels at depth t: after stages
 // 0..t-1 every element has been combined over input index bits 0..t-1, and
@@ -31,6 +33,18 @@
 #define CHW_HD __host__ __device__ __forceinline__
 #else
 #define CHW_HD inline
+#endif
+
+// Padding shifts of the tile layout (pad() below); overridable at build time
+// to compare layouts.
+#ifndef CHW_PAD1
+#define CHW_PAD1 5
+#endif
+#ifndef CHW_PAD2_15
+#define CHW_PAD2_15 10
+#endif
+#ifndef CHW_PAD2_12
+#define CHW_PAD2_12 10
 #endif
 
 namespace chw {
@@ -58,7 +72,7 @@ struct Layout {
     static constexpr int LNT = K - LR, NT = 1 << LNT;
     static constexpr int J = (K + LR - 1) / LR;          // register rounds
     // padding shifts: one word after every 2^P1 and every 2^P2 elements
-    static constexpr int P1 = 6, P2 = K >= 15 ? 12 : 11;
+    static constexpr int P1 = CHW_PAD1, P2 = K >= 15 ? CHW_PAD2_15 : CHW_PAD2_12;
     static_assert(LR >= 3 && LNT >= 6, "tile needs >= 8 registers and >= 1 wave");
 
     static CHW_HD constexpr int pad(int e) { return e + (e >> P1) + (e >> P2); }
@@ -106,13 +120,12 @@ struct Layout {
     template <int V, int C>
     static CHW_HD constexpr int transp_rot()
     {
-        // (K, V, C) -> rotation found with the bank model
+        // (K, V, C) -> rotation found with the bank rule above for the
+        // compiled row counts (V = 2: the FP64 tiles, 2^12 elements only)
         if constexpr (K >= 15)
-            return V == 4 ? (C == 3 ? 8 : C >= 5 ? C - 1 : 0)
-                          : (C == 3 ? 10 : C == 5 ? 6 : C == 6 ? 7 : 0);
+            return V == 4 ? (C == 5 ? 3 : C == 3 ? 1 : 0) : 0;
         else
-            return V == 4 ? (C == 3 ? 1 : C >= 4 && C <= 6 ? C - 1 : 0)
-                          : (C == 4 ? 5 : C == 5 ? 6 : 0);
+            return V == 4 ? (C == 6 ? 4 : C == 4 ? 2 : C == 3 ? 1 : 0) : (C == 4 ? 4 : 0);
     }
     template <int V, int C>
     static CHW_HD constexpr int transp_q(int n)

@@ -205,19 +205,21 @@ def test_layout_selfcheck():
     assert ok, [r for r in rep if not r.get("ok", True)]
     phases = {r["phase"] for r in rep if "phase" in r}
     assert phases == {"rounds", "contig", "paley", "paley_blocks_2^8..2^(K-1)", "transposed"}
-    # every phase of a compiled tile keeps a wave access within two words per
-    # LDS bank (64 banks, and 32 banks per half wave); the transposed phase is
-    # compiled for 2^7 / 2^5 / 2^3 rows in 2^15 tiles and 2^6 / 2^4 / 2^3 rows in
-    # 2^12 tiles
+    # 4-byte LDS accesses on gfx950: 32 banks per half-wave.  Every phase of a
+    # compiled 4-byte tile (16-byte vectors of 4 words, V = 4, or of 8 BF16 /
+    # FP16 elements, V = 8) puts at most one word per bank into a half-wave
+    # access; the FP64 tiles (V = 2, 8-byte words) at most two.  The
+    # transposed phase is compiled for 2^7 / 2^5 / 2^3 rows in 2^15 tiles and
+    # 2^6 / 2^4 / 2^3 rows in 2^12 tiles.
     compiled_rows = {12: (6, 4, 3), 15: (7, 5, 3)}
     for r in rep:
         if "phase" not in r:
             continue
         if r["phase"] == "transposed" and r["rows_log2"] not in compiled_rows[r["K"]]:
             continue
-        if r["phase"] == "transposed" and r["K"] == 15 and r["V"] == 2:
+        if r.get("V") == 2 and r["K"] == 15:
             continue  # no FP64 2^15 tiles
-        assert r["ways64"] <= 2 and r["ways32"] <= 2, r
+        assert r["ways32"] <= (2 if r.get("V") == 2 else 1), r
 
 
 @pytest.mark.parametrize("seed", range(6))
