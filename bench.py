@@ -42,17 +42,26 @@ def log(*a):
 TRANSFORM_SOURCES = ("chw_engine.h", "chw_layout.h", "chw_types.h", "chw_kernels.inc")
 
 
+def _code_only(text):
+    """C++ source without comments and blank space (the sources hold no string
+    literal with comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """Hash of the sources of the transform kernels: a stored traffic figure
-    is valid only for the kernels it was measured with (and for the same pass
-    splits, which the profile records too)."""
+    """Hash of the code of the transform kernels (comments and layout
+    ignored): a stored traffic figure is valid only for the kernels it was
+    measured with (and for the same pass splits, which the profile records
+    too)."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1609_06641_amd", "csrc", "*"))):
         b = os.path.basename(f)
         if b in TRANSFORM_SOURCES or (b.startswith("chw_kernels_") and b.endswith(".hip")):
-            with open(f, "rb") as fh:
+            with open(f) as fh:
                 h.update(os.path.basename(f).encode())
-                h.update(fh.read())
+                h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

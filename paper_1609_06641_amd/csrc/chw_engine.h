@@ -914,13 +914,14 @@ struct Engine {
     // consecutive positions -- 2^CC whole first-pass rows of round r + 1.
     // turn_round0 takes round r + 1's first register round straight from that
     // state: thread t reads the 2^LR consecutive output positions its register
-    // round covers through the last pass's Paley map, scales them, applies
-    // round r + 1's diagonal, runs the round's stages and writes them back in
-    // natural order; the remaining register rounds and the transposed store
-    // follow as in a first-pass tile.  Operands and their order are those of a
-    // last-pass store, a reload and a first-pass load, so the numbers are the
-    // same, with one HBM pass fewer.
-    //
+    // round covers through the last pass's Paley map, runs round r's last LR
+    // stages, scales the values, applies round r + 1's diagonal, runs round
+    // r + 1's first stages and writes the values back in natural order; the
+    // remaining register rounds and the transposed store follow as in a
+    // first-pass tile.  Operands and their order are those of a last-pass
+    // store, a reload and a first-pass load, so the numbers are the same, with
+    // one HBM pass fewer.
+
     // Sign bits of n <= 64 consecutive positions starting at bit b0 of the
     // diagonal (as many words as the window touches).
     static __device__ __forceinline__ uint64_t sign_window(const uint32_t *w, int64_t b0, int n)
@@ -934,7 +935,6 @@ struct Engine {
         return r;
     }
 
-    //
     // Register i of thread t holds tile element brev_low(o0 + i, bits): its
     // register bits b are tile bits bits - 1 - b, so the last LR stages of
     // round r (tile bits bits - LR .. bits - 1, in that order) run here too,
@@ -991,6 +991,7 @@ struct Engine {
     // pass's Paley gather would have put it at, and the tile continues as
     // round r - 1's adjoint last-pass tile (stages down to L1, contiguous store
     // to the next intermediate).
+
     // Register rounds J - 1 .. 1 of an adjoint pass (register round 0, tile
     // bits 0 .. LR - 1, left out).
     template <int j>

@@ -71,3 +71,8 @@ def test_profiles_name_their_kernels():
     p.set_option("split_l1", 8)
     with open(bench.PROFILE_HEADLINE) as f:
         assert bench.plan_launches(p, 0)[0]["symbol"] in f.read()
+
+
+def test_source_hash_ignores_comments():
+    assert bench._code_only("a // x\n  b /* y\n z */ c\n") == "a b c"
+    assert bench._code_only("int x = 1;  // one") == bench._code_only("int x = 1;\n")
