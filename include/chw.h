@@ -324,9 +324,12 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               2^15-element tiles, and the chunks' intermediates alternate
  *               between two workspace slots (0: passes of a chunk in separate
  *               launches).
- *   "stream"    1 (default): a launch (exec 0) of 2^15-element tiles that
- *               are all full and of one kind runs as a loop over its items,
- *               fetching the next tile's vectors while the current tile runs;
+ *   "stream"    2: a launch (exec 0) of 2^15-element tiles that are all
+ *               full and of one kind runs as a loop over its items, fetching
+ *               the next tile's vectors while the current tile runs;
+ *               1 (default): the same, except that a launch of single-pass
+ *               tiles prefetches only when every tile is one 2^15-element
+ *               signal and there are at least 1024 of them;
  *               0: one workgroup per tile.
  *   "timing"    1: record a HIP event around every launch (instrumentation;
  *               may be toggled at any time; disables graph replay)

@@ -974,7 +974,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
                     "exec 1 (dependency-counter work queue) is disabled");
     else if (k == "exec" && (value == 0 || value == 2)) cfg.exec = (int)value;
     else if (k == "chunk" && value >= 0) cfg.chunk = value;
-    else if (k == "stream" && (value == 0 || value == 1)) cfg.stream = (int)value;
+    else if (k == "stream" && value >= 0 && value <= 2) cfg.stream = (int)value;
     else if (k == "pipeline" && (value == 0 || value == 1)) cfg.pipeline = (int)value;
     else if (k == "turn" && (value == 0 || value == 1)) cfg.turn = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
@@ -1062,7 +1062,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
                 if (!has15 && s15 == 0) continue;
                 if (plan->dt == DT_F64 && (lr12 != 5 || lr15 != 5 || s15 != 1)) continue;
                 for (int l1 : l1s)
-                    for (int stream_mode : {0, 1}) {
+                    for (int stream_mode : {0, 1, 2}) {
                         PlanConfig c = plan->cfg;
                         c.lr12 = lr12;
                         c.lr15 = lr15;

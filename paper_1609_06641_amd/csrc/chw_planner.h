@@ -57,6 +57,10 @@ struct LaunchRange {
                          // call run inside the launch)
 };
 
+// Smallest launch of single-pass 2^15-element tiles that runs the prefetching
+// form.
+constexpr int kStreamBlocksMin = 1024;
+
 // Prefetching form of a launch of items [begin, end): 0 when the items are not
 // all full tiles of one kind without block lists, else 1 + that kind.
 int stream_source(const std::vector<Item> &items, int begin, int end, int K, bool adj);

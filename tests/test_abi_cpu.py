@@ -309,11 +309,20 @@ def test_stream_plan_shape():
     p = chw.Plan([13] * 8, dtype="f32", offsets=offs)
     assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [0]
     p.check()
-    # full single-pass tiles qualify
+    # full single-pass tiles of several signals prefetch only when forced
     p = chw.Plan([13] * 8, dtype="bf16")
+    assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [0]
+    p.set_option("stream", 2)
     assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [1]
+    p.check()
     with pytest.raises(chw.CHWError):
-        p.set_option("stream", 2)
+        p.set_option("stream", 3)
+    # one 2^15 signal per tile: from 1024 tiles on by default
+    for b, want in ((1023, 0), (1024, 1)):
+        p = chw.Plan([15] * b, dtype="f32")
+        assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [want], b
+        assert [r["stream"] for r in p.describe()["plan"]["backward"]] == [want], b
+        p.check()
 
 
 def test_plan_invariants_workloads():

@@ -211,15 +211,15 @@ def test_split_invariance_bitwise():
 def test_stream_bitwise(dtype):
     # launches of full 2^15-element tiles of one kind (single-pass 2^13 and
     # 2^15 signals, the first pass of 2^17 signals, both passes of 2^22
-    # signals) in the prefetching form, forward and backward, against the
-    # one-workgroup-per-tile form and the oracle
+    # signals) in the prefetching form (forced: mode 2), forward and
+    # backward, against the one-workgroup-per-tile form and the oracle
     for sizes in ([13] * 8, [15] * 2, [17] * 3, [22] * 2):
         gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
         x = np.concatenate([gen(900 + i, 1, k).reshape(-1) for i, k in enumerate(sizes)])
         xd = gu.dev_tensor(x, dtype)
         for lr in (5, 6):
             res = []
-            for stream in (0, 1):
+            for stream in (0, 2):
                 p = chw.Plan(sizes, dtype=dtype, norm="none" if dtype == "i32" else "ortho")
                 p.set_option("lr12", lr)
                 p.set_option("lr15", lr)
@@ -240,6 +240,27 @@ def test_stream_bitwise(dtype):
             ref = gu.oracle_packed(gu.host_f64(xd), sizes)
             tol = 4e-3 if dtype == "bf16" else 1e-5
             assert gu.per_signal_rel(res[1][0], ref, sizes).max() <= tol
+
+
+def test_stream_default_single_pass():
+    # the default prefetching rule picks the single-pass kernel for many
+    # one-signal 2^15-element tiles (1024 x 2^15): same bits as one
+    # workgroup per tile, and the oracle's values
+    sizes = [15] * 1024
+    x = workloads.float_signals(910, 1024, 15).reshape(-1)
+    xd = gu.dev_tensor(x, "f32")
+    res = []
+    for stream in (0, 1):
+        p = chw.Plan(sizes, dtype="f32")
+        p.set_option("stream", stream)
+        d = p.describe()["plan"]
+        assert [r["stream"] for r in d["forward"] + d["backward"]] == [stream, stream]
+        ws = gu.torch().empty(max(p.workspace_size(), 16), dtype=gu.torch().uint8, device="cuda")
+        res.append((gu.host_f64(p.forward(xd)), gu.host_f64(p.backward(xd, workspace=ws))))
+    _sync()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    ref = gu.oracle_packed(gu.host_f64(xd), sizes)
+    assert gu.per_signal_rel(res[1][0], ref, sizes).max() <= 1e-5
 
 
 @pytest.mark.skip(reason="the dependency-counter persistent kernel (exec 1) did not finish "

@@ -187,7 +187,7 @@ def test_signed_prefetching_tiles(mode):
         x = np.concatenate([workloads.float_signals(750 + i, 1, k)[0] for i, k in enumerate(sizes)])
         xd = gu.dev_tensor(x, "f32")
         res = []
-        for stream in (0, 1):
+        for stream in (0, 2):
             p = chw.Plan(sizes, dtype="f32")
             p.set_option("stream", stream)
             nbits = (1 << max(sizes)) if mode == "shared" else p.extent
