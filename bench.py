@@ -158,11 +158,10 @@ def roofline(bytes_per_elem, launches_ms, launches, profile, total_elems):
 
 # Planner options timed by default (the same kernels every run, so that the
 # stored profiles name them): the planner's own choices for the uniform
-# batches; for the ragged form one launch per pass replayed as a graph,
-# 2^12-element tiles with 2^6 registers and a first pass of 2^8 levels (the
-# autotuner's usual pick on this workload).
+# batches; for the ragged form one launch per pass replayed as a graph and a
+# first pass of 2^8 levels (the autotuner's usual pick on this workload).
 BENCH_CONFIG = {"plan": {},
-                "ragged": {"exec": 0, "lr12": 6, "lr15": 5, "single15": 1, "split_l1": 8,
+                "ragged": {"exec": 0, "lr15": 5, "single15": 1, "split_l1": 8,
                            "stream": 1}}
 
 

@@ -310,6 +310,7 @@ chw_status chw_plan_destroy(chw_plan_t plan);
 /* Override a planner choice before first use.  Keys (value):
  *   "split_l1"  levels of the first HBM pass of multi-pass signals (-1 = auto)
  *   "lr12"      5 or 6: log2 registers per thread of the 2^12-element tiles
+ *               (0, the default: 5 in single-pass launches, 6 in the others)
  *   "lr15"      5 or 6: log2 registers per thread of the 2^15-element tiles
  *   "single15"  1: signals of 2^13..2^15 in one pass; 0: two passes
  *   "chunk"     elements of multi-pass signals per first/last pass pair

@@ -965,7 +965,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     }
     if (plan->used) return fail(CHW_ERR_INVALID_ARGUMENT, "plan already used; options are fixed");
     PlanConfig cfg = plan->cfg;
-    if (k == "lr12" && (value == 5 || value == 6)) cfg.lr12 = (int)value;
+    if (k == "lr12" && (value == 0 || value == 5 || value == 6)) cfg.lr12 = (int)value;
     else if (k == "lr15" && (value == 5 || value == 6)) cfg.lr15 = (int)value;
     else if (k == "single15" && (value == 0 || value == 1)) cfg.single15 = (int)value;
     else if (k == "split_l1" && value >= -1 && value <= 30) cfg.split_l1 = (int)value;

@@ -274,15 +274,15 @@ struct Engine {
         }
     }
 
-    template <int j, bool ADJ>
+    template <int j, bool ADJ, int B0 = 0>
     static __device__ __forceinline__ void round(C *lds, int nst, int t)
     {
-        constexpr int lo = L::flo(j), a0 = L::alo(j), a1 = L::ahi(j);
+        constexpr int lo = L::flo(j, B0), a0 = L::alo(j, B0), a1 = L::ahi(j, B0);
         if (a0 >= nst) return;  // no active stage in this round (uniform)
-        C *base = lds + L::pad(L::round_tbase(j, t));
+        C *base = lds + L::pad(L::round_tbase(j, t, B0));
         C v[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = base[L::pad(L::round_reg(j, i))];
+        for (int i = 0; i < R; ++i) v[i] = base[L::pad(L::round_reg(j, i, B0))];
         if constexpr (!ADJ) {
 #pragma unroll
             for (int bit = a0; bit < a1; ++bit)
@@ -293,17 +293,19 @@ struct Engine {
                 if (bit < nst) bfly(v, bit - lo);
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) base[L::pad(L::round_reg(j, i))] = v[i];
+        for (int i = 0; i < R; ++i) base[L::pad(L::round_reg(j, i, B0))] = v[i];
         __syncthreads();
     }
 
-    template <bool ADJ, int j = 0>
+    // the stages [B0 + j LR, nst) (forward) or [0, nst) (adjoint, B0 = 0)
+    template <bool ADJ, int j = 0, int B0 = 0>
     static __device__ __forceinline__ void rounds(C *lds, int nst, int t)
     {
-        if constexpr (j < J) {
+        static_assert(!ADJ || B0 == 0, "the adjoint rounds start at bit 0");
+        if constexpr (j < L::rounds_from(B0)) {
             if constexpr (!ADJ) {
-                round<j, false>(lds, nst, t);
-                rounds<false, j + 1>(lds, nst, t);
+                round<j, false, B0>(lds, nst, t);
+                rounds<false, j + 1, B0>(lds, nst, t);
             } else {
                 round<J - 1 - j, true>(lds, nst, t);
                 rounds<true, j + 1>(lds, nst, t);
@@ -364,8 +366,27 @@ struct Engine {
     // ---- contiguous phases ---------------------------------------------------
     // Tile element e <-> memory element (block e >> bits at its base) + (e &
     // (2^bits - 1)).  Blocks are consecutive from `off` unless `list` gives
-    // their bases.  Only the first `count` blocks exist.
-    template <bool H, typename T>
+    // their bases.  Only the first `count` blocks exist.  PRE > 0: a loaded
+    // vector holds every value of tile bits [0, PRE) of its block, and stages
+    // 0 .. PRE - 1 run on it (after the signs) before it goes to LDS.
+    template <int V, int PRE>
+    static __device__ __forceinline__ void pre_stages(C *v, int bits)
+    {
+        static_assert((1 << PRE) <= V, "pre-stages stay inside one vector");
+#pragma unroll
+        for (int b = 0; b < PRE; ++b) {
+            if (b >= bits) break;  // uniform
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                if (!(i & (1 << b))) {
+                    C x = v[i], y = v[i | (1 << b)];
+                    v[i] = x + y;
+                    v[i | (1 << b)] = x - y;
+                }
+        }
+    }
+
+    template <bool H, typename T, int PRE = 0>
     static __device__ __forceinline__ void load_contig(C *lds, const T *src, int64_t off,
                                                        int bits, int count,
                                                        const int64_t *list, int t,
@@ -390,6 +411,10 @@ struct Engine {
                     for (int u = 0; u < V; ++u) vals[k][u] = apply_sign(vals[k][u], (sb >> u) & 1u);
                 }
             }
+            if constexpr (PRE > 0) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) pre_stages<V, PRE>(vals[k], bits);
+            }
 #pragma unroll
             for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -407,6 +432,7 @@ struct Engine {
 #pragma unroll
                         for (int u = 0; u < V; ++u) vals[k][u] = apply_sign(vals[k][u], (sb >> u) & 1u);
                     }
+                    if constexpr (PRE > 0) pre_stages<V, PRE>(vals[k], bits);
 #pragma unroll
                     for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[k][u];
                 }
@@ -1107,10 +1133,47 @@ struct Engine {
         }
     }
 
+    // ---- single-pass 2^12-element tiles with 2^5 registers ---------------------
+    // A 16-byte vector of the contiguous load holds every value of tile bits
+    // [0, lv), lv = log2 of its element count: stages 0 .. lv - 1 run on the
+    // loaded vectors and the register rounds cover bits [lv, 12) -- two rounds
+    // instead of three, one LDS round trip fewer.  Same stages, operands and
+    // order as the plain rounds, so the same bits.  (Other tile shapes keep
+    // their round count, so they load plainly.)
+    static constexpr int pre_bits()
+    {
+        return Vec<S>::V == 8 ? 3 : Vec<S>::V == 4 ? 2 : Vec<S>::V == 2 ? 1 : 0;
+    }
+    template <bool ADJ, int ORD>
+    static constexpr bool pre_ok()
+    {
+        return !ADJ && ORD == ORDER_DYADIC && K == 12 && LR == 5 && sizeof(C) == 4 &&
+               L::rounds_from(pre_bits()) < J;
+    }
+
+    static __device__ __forceinline__ void blocks_pre(const Item &it, const LaunchArgs &a,
+                                                      C *lds, int t)
+    {
+        constexpr int P = pre_bits();
+        const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
+        load_contig<NT_IN, S, P>(lds, static_cast<const S *>(a.in), it.io_off, it.bits, it.count,
+                                 list, t, SignCtx{a.signs, 0, a.sign_shared});
+        __syncthreads();
+        rounds<false, 0, P>(lds, it.bits, t);
+        store_paley<NT_OUT, S>(lds, static_cast<S *>(a.out), it.io_off, it.bits, it.count, list, t,
+                               ortho_scale<C>(it.m), a.ortho != 0);
+    }
+
     template <bool ADJ, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void run_item(const Item &it, const LaunchArgs &a,
                                                     C *lds, int t)
     {
+        if constexpr (pre_ok<ADJ, ORD>()) {
+            if (it.kind == KIND_BLOCKS && a.rounds <= 1) {
+                blocks_pre(it, a, lds, t);
+                return;
+            }
+        }
         load_item<ADJ, ORD>(it, a, lds, t);
         __syncthreads();
         finish_item<ADJ, ORD>(it, a, lds, t);

@@ -70,7 +70,7 @@ struct Layout {
     static constexpr int K = K_, LR = LR_;
     static constexpr int N = 1 << K, R = 1 << LR;
     static constexpr int LNT = K - LR, NT = 1 << LNT;
-    static constexpr int J = (K + LR - 1) / LR;          // register rounds
+    static constexpr int J = (K + LR - 1) / LR;          // register rounds (from bit 0)
     // padding shifts: one word after every 2^P1 and every 2^P2 elements
     static constexpr int P1 = CHW_PAD1, P2 = K >= 15 ? CHW_PAD2_15 : CHW_PAD2_12;
     static_assert(LR >= 3 && LNT >= 6, "tile needs >= 8 registers and >= 1 wave");
@@ -81,17 +81,26 @@ struct Layout {
     // ---- register rounds -------------------------------------------------
     // Round j makes active the tile bits [alo(j), ahi(j)); the register field
     // is [flo(j), flo(j) + LR) (the last round's field is moved down so that it
-    // stays inside the tile and holds R elements).
-    static CHW_HD constexpr int alo(int j) { return j * LR; }
-    static CHW_HD constexpr int ahi(int j) { return (j + 1) * LR < K ? (j + 1) * LR : K; }
-    static CHW_HD constexpr int flo(int j) { return j * LR < K - LR ? j * LR : K - LR; }
+    // stays inside the tile and holds R elements).  With B0 > 0 the rounds
+    // start at tile bit B0: the stages below it ran on the loaded vectors
+    // before the tile reached LDS.
+    static CHW_HD constexpr int rounds_from(int B0) { return (K - B0 + LR - 1) / LR; }
+    static CHW_HD constexpr int alo(int j, int B0 = 0) { return B0 + j * LR; }
+    static CHW_HD constexpr int ahi(int j, int B0 = 0)
+    {
+        return B0 + (j + 1) * LR < K ? B0 + (j + 1) * LR : K;
+    }
+    static CHW_HD constexpr int flo(int j, int B0 = 0)
+    {
+        return B0 + j * LR < K - LR ? B0 + j * LR : K - LR;
+    }
     // tile element of (thread t, register 0) in round j: thread bits fill the
     // tile bits outside the register field, low to high
-    static CHW_HD constexpr int round_tbase(int j, int t)
+    static CHW_HD constexpr int round_tbase(int j, int t, int B0 = 0)
     {
-        return (t & ((1 << flo(j)) - 1)) | ((t >> flo(j)) << (flo(j) + LR));
+        return (t & ((1 << flo(j, B0)) - 1)) | ((t >> flo(j, B0)) << (flo(j, B0) + LR));
     }
-    static CHW_HD constexpr int round_reg(int j, int i) { return i << flo(j); }
+    static CHW_HD constexpr int round_reg(int j, int i, int B0 = 0) { return i << flo(j, B0); }
 
     // ---- contiguous phase (16-byte vectors of V elements) -----------------
     // vector q = t + NT*k covers tile elements [q*V, q*V + V)

@@ -15,7 +15,8 @@ namespace chw {
 // stages always run in the same order with the same operands, and the scale is
 // applied once at the final store.
 struct PlanConfig {
-    int lr12 = 6;       // register bits of the 2^12-element tile kernels (5, 6)
+    int lr12 = 0;       // register bits of the 2^12-element tile kernels (5, 6;
+                        // 0 = 5 in single-pass launches, 6 in the others)
     int lr15 = 5;       // register bits of the 2^15-element tile kernels (5, 6)
     int single15 = 1;   // signals with 13 <= m <= 15 in one pass of a 2^15 tile
     int split_l1 = -1;  // forced first-pass level count of multi-pass signals

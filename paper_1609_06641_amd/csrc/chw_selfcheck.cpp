@@ -62,34 +62,51 @@ std::string check_variant()
     std::string out;
     char buf[512];
 
-    // ---- rounds
-    Stats rs;
-    for (int j = 0; j < L::J; ++j) {
-        std::vector<int> seen(N, 0);
-        for (int t = 0; t < NT; ++t)
-            for (int i = 0; i < R; ++i) {
-                const int tb = L::round_tbase(j, t), ri = L::round_reg(j, i);
-                if (tb & ri) rs.fail("round fields overlap");
-                const int e = tb | ri;
-                if (e < 0 || e >= N) { rs.fail("round element out of range"); continue; }
-                ++seen[e];
-                if (L::pad(tb) + L::pad(ri) != L::pad(e)) rs.fail("round offset split");
-                if (L::pad(e) >= L::LDS_WORDS) rs.fail("round LDS address out of range");
-            }
-        for (int e = 0; e < N; ++e)
-            if (seen[e] != 1) { rs.fail("round map not bijective"); break; }
-        for (int w = 0; w < NT / 64; ++w)
-            for (int i = 0; i < R; ++i) {
-                std::vector<int> a;
-                for (int l = 0; l < 64; ++l)
-                    a.push_back(L::pad(L::round_tbase(j, 64 * w + l) | L::round_reg(j, i)));
-                bank_account(rs, a);
-            }
+    // ---- rounds (from tile bit B0: B0 > 0 after stages on the loaded vectors)
+    auto rounds_phase = [&](int B0) {
+        Stats rs;
+        int covered = 0;
+        for (int j = 0; j < L::rounds_from(B0); ++j) {
+            if (L::flo(j, B0) > L::alo(j, B0) || L::alo(j, B0) >= L::ahi(j, B0) ||
+                L::ahi(j, B0) > L::flo(j, B0) + LR || L::alo(j, B0) != B0 + covered)
+                rs.fail("round active bits outside the register field");
+            covered = L::ahi(j, B0) - B0;
+            std::vector<int> seen(N, 0);
+            for (int t = 0; t < NT; ++t)
+                for (int i = 0; i < R; ++i) {
+                    const int tb = L::round_tbase(j, t, B0), ri = L::round_reg(j, i, B0);
+                    if (tb & ri) rs.fail("round fields overlap");
+                    const int e = tb | ri;
+                    if (e < 0 || e >= N) { rs.fail("round element out of range"); continue; }
+                    ++seen[e];
+                    if (L::pad(tb) + L::pad(ri) != L::pad(e)) rs.fail("round offset split");
+                    if (L::pad(e) >= L::LDS_WORDS) rs.fail("round LDS address out of range");
+                }
+            for (int e = 0; e < N; ++e)
+                if (seen[e] != 1) { rs.fail("round map not bijective"); break; }
+            for (int w = 0; w < NT / 64; ++w)
+                for (int i = 0; i < R; ++i) {
+                    std::vector<int> a;
+                    for (int l = 0; l < 64; ++l)
+                        a.push_back(L::pad(L::round_tbase(j, 64 * w + l, B0) | L::round_reg(j, i, B0)));
+                    bank_account(rs, a);
+                }
+        }
+        if (covered != K - B0) rs.fail("rounds do not cover the tile bits");
+        std::snprintf(buf, sizeof buf, "%s{\"K\": %d, \"LR\": %d, \"phase\": \"%s\", \"B0\": %d, \"rounds\": %d, \"ok\": %s, \"ways64\": %d, \"ways32\": %d%s%s}",
+                      B0 ? ", " : "", K, LR, B0 ? "rounds_from_bit" : "rounds", B0, L::rounds_from(B0),
+                      rs.ok ? "true" : "false", rs.worst64, rs.worst32,
+                      rs.ok ? "" : ", \"error\": \"", rs.ok ? "" : (rs.err + "\"").c_str());
+        out += buf;
+    };
+    rounds_phase(0);
+    // single-pass 2^12-element tiles with 2^5 registers start their rounds
+    // after the stages on the loaded 16-byte vectors: bit 2 (4-byte
+    // elements) or bit 3 (2-byte elements)
+    if (K == 12 && LR == 5) {
+        rounds_phase(2);
+        rounds_phase(3);
     }
-    std::snprintf(buf, sizeof buf, "{\"K\": %d, \"LR\": %d, \"phase\": \"rounds\", \"ok\": %s, \"ways64\": %d, \"ways32\": %d%s%s}",
-                  K, LR, rs.ok ? "true" : "false", rs.worst64, rs.worst32,
-                  rs.ok ? "" : ", \"error\": \"", rs.ok ? "" : (rs.err + "\"").c_str());
-    out += buf;
 
     // ---- vector phases
     auto vec_phase = [&](auto vtag) {

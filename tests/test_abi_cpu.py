@@ -204,7 +204,12 @@ def test_layout_selfcheck():
     ok, rep = chw.layout_selfcheck()
     assert ok, [r for r in rep if not r.get("ok", True)]
     phases = {r["phase"] for r in rep if "phase" in r}
-    assert phases == {"rounds", "contig", "paley", "paley_blocks_2^8..2^(K-1)", "transposed"}
+    assert phases == {"rounds", "rounds_from_bit", "contig", "paley", "paley_blocks_2^8..2^(K-1)",
+                      "transposed"}
+    # single-pass 2^12 tiles with 2^5 registers: two rounds after the stages
+    # on the loaded vectors, against three from bit 0
+    pre = {(r["K"], r["LR"], r["B0"]): r["rounds"] for r in rep if r.get("phase", "").startswith("rounds")}
+    assert pre[(12, 5, 0)] == 3 and pre[(12, 5, 2)] == 2 and pre[(12, 5, 3)] == 2
     # 4-byte LDS accesses on gfx950: 32 banks per half-wave.  Every phase of a
     # compiled 4-byte tile (16-byte vectors of 4 words, V = 4, or of 8 BF16 /
     # FP16 elements, V = 8) puts at most one word per bank into a half-wave
