@@ -367,15 +367,16 @@ struct Engine {
     // Tile element e <-> memory element (block e >> bits at its base) + (e &
     // (2^bits - 1)).  Blocks are consecutive from `off` unless `list` gives
     // their bases.  Only the first `count` blocks exist.  PRE > 0: a loaded
-    // vector holds every value of tile bits [0, PRE) of its block, and stages
-    // 0 .. PRE - 1 run on it (after the signs) before it goes to LDS.
+    // vector holds every value of tile bits [0, PRE) of its block, and the
+    // stages below min(PRE, pre_lim) run on it (after the signs) before it
+    // goes to LDS.
     template <int V, int PRE>
-    static __device__ __forceinline__ void pre_stages(C *v, int bits)
+    static __device__ __forceinline__ void pre_stages(C *v, int lim)
     {
         static_assert((1 << PRE) <= V, "pre-stages stay inside one vector");
 #pragma unroll
         for (int b = 0; b < PRE; ++b) {
-            if (b >= bits) break;  // uniform
+            if (b >= lim) break;  // uniform
 #pragma unroll
             for (int i = 0; i < V; ++i)
                 if (!(i & (1 << b))) {
@@ -390,7 +391,8 @@ struct Engine {
     static __device__ __forceinline__ void load_contig(C *lds, const T *src, int64_t off,
                                                        int bits, int count,
                                                        const int64_t *list, int t,
-                                                       const SignCtx &sg = SignCtx{nullptr, 0, 0})
+                                                       const SignCtx &sg = SignCtx{nullptr, 0, 0},
+                                                       int pre_lim = 0)
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         static_assert(NV >= 1, "tile too small for the vector width");
@@ -413,7 +415,7 @@ struct Engine {
             }
             if constexpr (PRE > 0) {
 #pragma unroll
-                for (int k = 0; k < NV; ++k) pre_stages<V, PRE>(vals[k], bits);
+                for (int k = 0; k < NV; ++k) pre_stages<V, PRE>(vals[k], pre_lim);
             }
 #pragma unroll
             for (int k = 0; k < NV; ++k)
@@ -432,7 +434,7 @@ struct Engine {
 #pragma unroll
                         for (int u = 0; u < V; ++u) vals[k][u] = apply_sign(vals[k][u], (sb >> u) & 1u);
                     }
-                    if constexpr (PRE > 0) pre_stages<V, PRE>(vals[k], bits);
+                    if constexpr (PRE > 0) pre_stages<V, PRE>(vals[k], pre_lim);
 #pragma unroll
                     for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[k][u];
                 }
@@ -997,12 +999,20 @@ struct Engine {
         __syncthreads();
     }
 
+    // A round-boundary tile loads the intermediate contiguously and runs the
+    // stages below min(turn_pre(), bits - LR) on the loaded vectors (both
+    // load forms), so round r's remaining early stages start at that bit:
+    // with 2^5 registers and 2^12-element last-pass blocks, stages 2 .. 6 in
+    // one register round instead of 0 .. 6 in two.  (With 2^6 registers those
+    // stages fit one round from bit 0 already.)
+    static constexpr int turn_pre() { return LR == 5 ? pre_bits<C>() : 0; }
+
     template <int CC>
     static __device__ __forceinline__ void finish_turn_cc(const Item &it, const LaunchArgs &a,
                                                           C *lds, int t)
     {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
-        rounds<false>(lds, it.bits - LR, t);  // round r's stages below the last LR
+        rounds<false, 0, turn_pre()>(lds, it.bits - LR, t);  // round r's stages below the last LR
         turn_round0(it, a, K - CC, lds, t);
         rounds<false, 1>(lds, K - CC, t);
         const int64_t base = a.inter2_is_io ? it.sig_off
@@ -1140,24 +1150,26 @@ struct Engine {
     // instead of three, one LDS round trip fewer.  Same stages, operands and
     // order as the plain rounds, so the same bits.  (Other tile shapes keep
     // their round count, so they load plainly.)
+    // log2 of the elements of type T in one 16-byte vector
+    template <typename T>
     static constexpr int pre_bits()
     {
-        return Vec<S>::V == 8 ? 3 : Vec<S>::V == 4 ? 2 : Vec<S>::V == 2 ? 1 : 0;
+        return Vec<T>::V == 8 ? 3 : Vec<T>::V == 4 ? 2 : Vec<T>::V == 2 ? 1 : 0;
     }
     template <bool ADJ, int ORD>
     static constexpr bool pre_ok()
     {
         return !ADJ && ORD == ORDER_DYADIC && K == 12 && LR == 5 && sizeof(C) == 4 &&
-               L::rounds_from(pre_bits()) < J;
+               L::rounds_from(pre_bits<S>()) < J;
     }
 
     static __device__ __forceinline__ void blocks_pre(const Item &it, const LaunchArgs &a,
                                                       C *lds, int t)
     {
-        constexpr int P = pre_bits();
+        constexpr int P = pre_bits<S>();
         const int64_t *list = it.list >= 0 ? a.list + it.list : nullptr;
         load_contig<NT_IN, S, P>(lds, static_cast<const S *>(a.in), it.io_off, it.bits, it.count,
-                                 list, t, SignCtx{a.signs, 0, a.sign_shared});
+                                 list, t, SignCtx{a.signs, 0, a.sign_shared}, it.bits);
         __syncthreads();
         rounds<false, 0, P>(lds, it.bits, t);
         store_paley<NT_OUT, S>(lds, static_cast<S *>(a.out), it.io_off, it.bits, it.count, list, t,
@@ -1258,6 +1270,7 @@ struct Engine {
                         for (int u = 0; u < V; ++u) vals[u] = apply_sign(vals[u], (sw[k] >> u) & 1u);
                     }
                 }
+                if constexpr (KIND == KIND_TURN) pre_stages<V, turn_pre()>(vals, it.bits - LR);
 #pragma unroll
                 for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[u];
             }

@@ -100,13 +100,15 @@ std::string check_variant()
         out += buf;
     };
     rounds_phase(0);
-    // single-pass 2^12-element tiles with 2^5 registers start their rounds
-    // after the stages on the loaded 16-byte vectors: bit 2 (4-byte
-    // elements) or bit 3 (2-byte elements)
+    // rounds after the stages on the loaded 16-byte vectors: single-pass
+    // 2^12-element tiles with 2^5 registers start at bit 2 (4-byte elements)
+    // or bit 3 (2-byte elements), the round-boundary 2^15-element tiles with
+    // 2^5 registers at bit 2 (4-byte intermediate)
     if (K == 12 && LR == 5) {
         rounds_phase(2);
         rounds_phase(3);
     }
+    if (K == 15 && LR == 5) rounds_phase(2);
 
     // ---- vector phases
     auto vec_phase = [&](auto vtag) {

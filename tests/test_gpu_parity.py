@@ -242,6 +242,53 @@ def test_stream_bitwise(dtype):
             assert gu.per_signal_rel(res[1][0], ref, sizes).max() <= tol
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16", "i32"])
+def test_vector_stages_bitwise(dtype):
+    # single-pass 2^12-element tiles with 2^5 registers run their first stages
+    # on the loaded 16-byte vectors (two register rounds); with 2^6 registers
+    # they load plainly (two rounds from bit 0).  Same bits, with gaps between
+    # the signals (block lists), partial tiles and a signed round.
+    rng = np.random.default_rng(77)
+    ms = [int(k) for k in rng.integers(3, 13, size=61)] + [12] * 5 + [3] * 9
+    align = 8
+    offs, o = [], 0
+    for k in ms:
+        o += int(rng.integers(0, 2)) * align
+        offs.append(o)
+        o += max(1 << k, align)
+    offs.append(o)
+    offs = np.array(offs, dtype=np.int64)
+    total = int(offs[-1])
+    norm = "none" if dtype == "i32" else "ortho"
+    x = (rng.integers(-128, 128, size=total).astype(np.int32) if dtype == "i32"
+         else rng.standard_normal(total).astype(np.float32))
+    xd = gu.dev_tensor(x, dtype)
+    t = gu.torch()
+    res = []
+    for lr in (5, 6):
+        p = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs)
+        p.set_option("lr12", lr)
+        d = p.describe()["plan"]
+        assert {r["LR"] for r in d["forward"] if r["K"] == 12} == {lr}
+        s = p.philox_signs(78, 1, "per_element")
+        y = t.zeros_like(xd)
+        ys = t.zeros_like(xd)
+        p.forward(xd, out=y)
+        p.forward_signed(xd, s, "per_element", 1, out=ys)
+        res.append((y, ys))
+    _sync()
+    assert t.equal(res[0][0], res[1][0]) and t.equal(res[0][1], res[1][1])
+    if dtype == "i32":
+        ref = gu.oracle_packed(x.astype(np.int64), ms, offs)
+        mask = np.zeros(total, dtype=bool)
+        for k, o in zip(ms, offs[:-1]):
+            mask[o:o + (1 << k)] = True
+        assert np.array_equal(gu.host_i64(res[0][0])[mask], ref[mask])
+    else:
+        ref = gu.oracle_packed(gu.host_f64(xd), ms, offs)
+        assert gu.per_signal_rel(gu.host_f64(res[0][0]), ref, ms, offs).max() <= gu.TOL[dtype]
+
+
 def test_stream_default_single_pass():
     # the default prefetching rule picks the single-pass kernel for many
     # one-signal 2^15-element tiles (1024 x 2^15): same bits as one
