@@ -182,9 +182,14 @@ chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes);
 chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
                        void *stream);
 
-/* chw_backward -- y_i = H_{m_i}^T g_i: the adjoint of eq. (3), applied as the
- * transposed factors in reverse order (Haar synthesis).  Same arguments and
- * rules as chw_forward. */
+/* chw_backward -- y_i = H_{m_i}^T g_i: the adjoint of eq. (3), the transposed
+ * factors in reverse order (Haar synthesis).  In the dyadic order H_m is
+ * symmetric and the synthesis cascade adds the same pairs in the same order
+ * as the forward one (on positions relabelled by the bit reversal), so by
+ * default a dyadic-order plan runs the forward launches, which give the same
+ * bits faster; option "adjoint" = 1 runs the synthesis kernels instead.
+ * Plans of the other orders always run the synthesis kernels.  Same
+ * arguments and rules as chw_forward. */
 chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace,
                         void *stream);
 
@@ -332,6 +337,9 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               tiles prefetches only when every tile is one 2^15-element
  *               signal and there are at least 1024 of them;
  *               0: one workgroup per tile.
+ *   "adjoint"   0 (default): chw_backward of a dyadic-order plan runs the
+ *               forward launches (same bits, see chw_backward); 1: the Haar
+ *               synthesis kernels.
  *   "timing"    1: record a HIP event around every launch (instrumentation;
  *               may be toggled at any time; disables graph replay)
  * Unknown keys or values give CHW_ERR_INVALID_ARGUMENT; so does changing a

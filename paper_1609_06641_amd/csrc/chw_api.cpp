@@ -710,7 +710,10 @@ chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
 
 chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace, void *stream)
 {
-    return run(plan, 1, g, y, workspace, stream);
+    // dyadic order: H^T = H, and the forward launches give the adjoint
+    // cascade's bits (option "adjoint" selects the synthesis kernels)
+    const bool synth = !plan || plan->cfg.order != ORDER_DYADIC || plan->cfg.adjoint;
+    return run(plan, synth ? 1 : 0, g, y, workspace, stream);
 }
 
 static chw_status run_haar(chw_plan_t p, int adj, const void *x, void *y, void *ws,
@@ -977,6 +980,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     else if (k == "stream" && value >= 0 && value <= 2) cfg.stream = (int)value;
     else if (k == "pipeline" && (value == 0 || value == 1)) cfg.pipeline = (int)value;
     else if (k == "turn" && (value == 0 || value == 1)) cfg.turn = (int)value;
+    else if (k == "adjoint" && (value == 0 || value == 1)) cfg.adjoint = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
     return rebuild(plan, cfg);
 }

@@ -35,6 +35,13 @@ struct PlanConfig {
                         // intermediate is read back soon after it is written
     int order = 0;      // coefficient order (Order): set from the plan's
                         // flags, not a tuning choice
+    int adjoint = 0;    // chw_backward of a dyadic-order plan: 0 runs the
+                        // forward launches (the Paley-ordered H is symmetric
+                        // and the adjoint cascade adds the same operands in
+                        // the same order, so the bits are the same); 1 runs
+                        // the synthesis cascade (transposed factors, reverse
+                        // order).  Signed and other-order calls always take
+                        // the synthesis cascade.
     int turn = 1;       // 1: signed multi-round forward calls join round r's
                         // last pass and round r + 1's first pass in one launch
                         // of KIND_TURN tiles where the plan qualifies

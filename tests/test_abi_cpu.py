@@ -524,3 +524,16 @@ def test_turn_plan_shape():
         r.set_option(key, val)
         r.check()
         assert r.describe()["plan"]["turn"] == [], key
+
+
+def test_adjoint_option():
+    # chw_backward of a dyadic plan runs the forward launches unless option
+    # "adjoint" asks for the synthesis kernels; the option is fixed on use
+    # like the planner choices
+    p = chw.Plan([20] * 2 + [9] * 3, dtype="f32")
+    assert p.describe()["plan"]["config"]["adjoint"] == 0
+    p.set_option("adjoint", 1)
+    assert p.describe()["plan"]["config"]["adjoint"] == 1
+    with pytest.raises(chw.CHWError):
+        p.set_option("adjoint", 2)
+    p.check()

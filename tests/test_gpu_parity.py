@@ -93,6 +93,7 @@ def test_backward_equals_forward_and_oracle(m):
     x = workloads.float_signals(300 + m, b, m).reshape(-1)
     sizes = [m] * b
     p = chw.Plan(sizes, dtype="f32")
+    p.set_option("adjoint", 1)  # the synthesis kernels (forward launches: next test)
     xd = gu.dev_tensor(x, "f32")
     yf = p.forward(xd)
     yb = p.backward(xd)
@@ -102,10 +103,42 @@ def test_backward_equals_forward_and_oracle(m):
     assert gu.per_signal_rel(gu.host_f64(yb), ref, sizes).max() <= 1e-5
     xi = workloads.int_signals(400 + m, b, m).reshape(-1)
     pi = chw.Plan(sizes, dtype="i32", norm="none")
+    pi.set_option("adjoint", 1)
     ybi = pi.backward(gu.dev_tensor(xi, "i32"))
     _sync()
     assert np.array_equal(gu.host_i64(ybi), gu.oracle_packed(xi.astype(np.int64), sizes,
                                                               adjoint=True))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "i32", "f64"])
+def test_backward_default_runs_forward_launches(dtype):
+    # chw_backward of a dyadic plan runs the forward launches by default; the
+    # synthesis kernels (option "adjoint" = 1) give the same bits, and so
+    # does the oracle's adjoint cascade up to rounding
+    rng = np.random.default_rng(81)
+    sizes = [int(k) for k in rng.integers(3, 13, size=40)] + ([16, 20, 14] if dtype != "f64" else [16, 14])
+    norm = "none" if dtype == "i32" else "ortho"
+    x = np.concatenate([(workloads.int_signals(810 + i, 1, k) if dtype == "i32"
+                         else workloads.float_signals(810 + i, 1, k)).reshape(-1)
+                        for i, k in enumerate(sizes)])
+    xd = gu.dev_tensor(x, dtype)
+    t = gu.torch()
+    p = chw.Plan(sizes, dtype=dtype, norm=norm)
+    q = chw.Plan(sizes, dtype=dtype, norm=norm)
+    q.set_option("adjoint", 1)
+    assert p.describe()["plan"]["config"]["adjoint"] == 0
+    ws = t.empty(max(p.workspace_size(), 16), dtype=t.uint8, device="cuda")
+    yf = p.forward(xd, workspace=ws)
+    yb = p.backward(xd, workspace=ws)
+    ys = q.backward(xd, workspace=ws)
+    _sync()
+    assert t.equal(yf, yb) and t.equal(yb, ys)
+    if dtype == "i32":
+        assert np.array_equal(gu.host_i64(yb), gu.oracle_packed(x.astype(np.int64), sizes,
+                                                                 adjoint=True))
+    else:
+        ref = gu.oracle_packed(gu.host_f64(xd), sizes, adjoint=True)
+        assert gu.per_signal_rel(gu.host_f64(yb), ref, sizes).max() <= gu.TOL[dtype]
 
 
 # ---------------------------------------------------------------------------
@@ -119,6 +152,7 @@ def test_precision_forms(dtype, m, batch):
     x64 = xh.to(gu.torch().float64).numpy().reshape(-1)  # exact
     sizes = [m] * batch
     p = chw.Plan(sizes, dtype=dtype)
+    p.set_option("adjoint", 1)  # backward through the synthesis kernels
     y = p.forward(gu.dev_tensor(xh.reshape(-1), dtype))
     yb = p.backward(gu.dev_tensor(xh.reshape(-1), dtype))
     _sync()
@@ -221,6 +255,7 @@ def test_stream_bitwise(dtype):
             res = []
             for stream in (0, 2):
                 p = chw.Plan(sizes, dtype=dtype, norm="none" if dtype == "i32" else "ortho")
+                p.set_option("adjoint", 1)
                 p.set_option("lr12", lr)
                 p.set_option("lr15", lr)
                 p.set_option("stream", stream)
@@ -325,6 +360,7 @@ def test_graph_replay():
                         for i, k in enumerate(sizes)])
     t = gu.torch()
     p = chw.Plan(sizes, dtype="f32", graph=True)
+    p.set_option("adjoint", 1)  # the backward graph holds the synthesis kernels
     plain = chw.Plan(sizes, dtype="f32")
     xd = gu.dev_tensor(x, "f32")
     ref = gu.host_f64(plain.forward(xd))
@@ -350,6 +386,7 @@ def test_f64_verify_kernel():
     x = np.concatenate([np.random.default_rng(700 + i).standard_normal(1 << k)
                         for i, k in enumerate(sizes)])
     p = chw.Plan(sizes, dtype="f64")
+    p.set_option("adjoint", 1)
     y = p.forward(gu.dev_tensor(x, "f64"))
     yb = p.backward(gu.dev_tensor(x, "f64"))
     _sync()
@@ -422,6 +459,7 @@ def test_persistent_ragged(dtype):
     plain = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs)
     for graph in (False, True):
         p = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs, persistent=True, graph=graph)
+        p.set_option("adjoint", 1)
         d = p.describe()["plan"]
         assert len(d["forward"]) == 1 and d["forward"][0]["persistent"] == 1
         xd = gu.dev_tensor(x, dtype)
