@@ -724,6 +724,58 @@ struct Engine {
         }
     }
 
+    // First-pass store that runs the row's top nk = log2(R / V) stages: a
+    // thread's vectors differ exactly in row-element bits L1 - nk .. L1 - 1
+    // (the low run-index bits), so those stages, in increasing order, pair
+    // whole vectors in registers; the element whose bit is clear (the earlier
+    // one in the row) takes the sum.  The global layout is the one of
+    // store_transp; only which thread writes which vector differs.  Used for
+    // 2^15-element tiles of 2^7 rows (L1 = 8) with 2^5 registers, where it
+    // leaves one register round (stages 0 .. 4) instead of two.
+    template <int CC, bool BR>
+    static constexpr bool merge_ok()
+    {
+        return BR && K == 15 && LR == 5 && CC == 7 && sizeof(C) == 4;
+    }
+    template <int CC>
+    static constexpr int merge_stages() { return LR - pre_bits<C>(); }
+
+    template <int CC>
+    static __device__ __forceinline__ void store_transp_merged(const C *lds, C *dst,
+                                                               int64_t base, int h0, int rs,
+                                                               int t)
+    {
+        constexpr int V = Vec<C>::V, NV = N / (V * NT), L1 = K - CC, nk = merge_stages<CC>();
+        static_assert((1 << nk) == NV && nk < L1, "one vector per value of the merged bits");
+        const C *lb = lds + L::pad(L::template transpm_e<V, CC>(t, 0, 0));
+        C vals[NV][V];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                vals[k][u] = lb[L::pad(L::template transpm_e<V, CC>(0, k, u))];
+#pragma unroll
+        for (int b = L1 - nk; b < L1; ++b) {
+            const int kb = L1 - 1 - b;  // row-element bit b is run-index bit L1 - 1 - b
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (!(k & (1 << kb))) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) {
+                        C x = vals[k][u], y = vals[k | (1 << kb)][u];
+                        vals[k][u] = x + y;
+                        vals[k | (1 << kb)][u] = x - y;
+                    }
+                }
+        }
+        C *d = dst + base + h0 +
+               L::template transp_goff<CC>(V * L::template transpm_q<V, CC>(t, 0), rs);
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            st16<NT_INTER>(d + L::template transp_goff<CC>(V * L::template transpm_q<V, CC>(0, k), rs),
+                           Vec<C>::encode(vals[k]));
+    }
+
     template <int CC, bool BR = true>
     static __device__ __forceinline__ void load_transp(C *lds, const C *src, int64_t base,
                                                        int h0, int rs, int t)
@@ -922,6 +974,11 @@ struct Engine {
                                          SignCtx{a.signs, 0, a.sign_shared});
         } else if constexpr (is_first_kind(KIND)) {
             constexpr int CC = rows_of<KIND>();
+            if constexpr (!ADJ && merge_ok<CC, BR>()) {
+                rounds<false>(lds, K - CC - merge_stages<CC>(), t);
+                store_transp_merged<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
+                return;
+            }
             rounds<ADJ>(lds, K - CC, t);
             if constexpr (!ADJ) store_transp<CC, BR>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
@@ -1014,10 +1071,16 @@ struct Engine {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
         rounds<false, 0, turn_pre()>(lds, it.bits - LR, t);  // round r's stages below the last LR
         turn_round0(it, a, K - CC, lds, t);
-        rounds<false, 1>(lds, K - CC, t);
         const int64_t base = a.inter2_is_io ? it.sig_off
                                             : it.ws_off - ((int64_t)it.h0 << (K - CC));
-        store_transp<CC, true>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
+        if constexpr (merge_ok<CC, true>()) {
+            // round r + 1's stages LR .. L1 - 1 are exactly the merged ones
+            static_assert(K - CC - merge_stages<CC>() == LR, "stages 0 .. LR - 1 ran in turn_round0");
+            store_transp_merged<CC>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
+        } else {
+            rounds<false, 1>(lds, K - CC, t);
+            store_transp<CC, true>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
+        }
     }
 
     // The adjoint's round boundary runs the other way: round r's adjoint

@@ -160,6 +160,28 @@ struct Layout {
         int rho = o >> C;
         return (hl << L1) | (BR ? (int)rbrev((uint32_t)rho, L1) : rho);
     }
+    // Merged variant (first-pass store that also runs the row's top stages):
+    // the R / V vectors of a thread differ in the low run-index bits, i.e. in
+    // row-element bits L1 - 1 .. L1 - log2(R / V), so the stages on those bits
+    // run in registers before the store.  Thread bits below C - lv pick the
+    // vector inside a run (lanes keep whole runs); the thread bits above go
+    // above the run-index bits that k takes.
+    template <int V, int C>
+    static CHW_HD constexpr int transpm_q(int t, int k)
+    {
+        constexpr int lv = V == 8 ? 3 : V == 4 ? 2 : V == 2 ? 1 : 0;
+        constexpr int wr = C - lv, nk = LR - lv;
+        return (t & ((1 << wr) - 1)) | (k << wr) | ((t >> wr) << (wr + nk));
+    }
+    template <int V, int C>
+    static CHW_HD int transpm_e(int t, int k, int u)
+    {
+        constexpr int L1 = K - C;
+        int o = V * transpm_q<V, C>(t, k) + u;
+        int hl = o & ((1 << C) - 1);
+        int rho = o >> C;
+        return (hl << L1) | (int)rbrev((uint32_t)rho, L1);
+    }
     // element offset (relative to the signal base + h0) of output o, given the
     // run stride 2^rs of the transposed layout
     template <int C>

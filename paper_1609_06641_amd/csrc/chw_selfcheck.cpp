@@ -239,6 +239,55 @@ std::string check_variant()
     tr_phase(std::integral_constant<int, 4>{}, std::integral_constant<int, 7>{});
     tr_phase(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
     tr_phase(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
+
+    // ---- merged transposed store of 2^15-element tiles with 2^5 registers and
+    // 2^7 rows (4-byte elements): same global layout as the plain store, and
+    // a thread's vector k covers run index bits 0 .. log2(R / V) - 1 = k
+    if constexpr (K == 15 && LR == 5) {
+        constexpr int V = 4, CC = 7, NV = N / (V * NT), L1 = K - CC;
+        Stats ms;
+        std::vector<int> seen(N, 0);
+        const int rsv = 13;
+        std::set<int64_t> gseen;
+        for (int t = 0; t < NT; ++t)
+            for (int k = 0; k < NV; ++k)
+                for (int u = 0; u < V; ++u) {
+                    const int e = L::template transpm_e<V, CC>(t, k, u);
+                    if (e < 0 || e >= N) { ms.fail("merged out of range"); continue; }
+                    ++seen[e];
+                    if (L::pad(L::template transpm_e<V, CC>(t, 0, 0)) +
+                            L::pad(L::template transpm_e<V, CC>(0, k, u)) != L::pad(e))
+                        ms.fail("merged offset split");
+                    const int qt = L::template transpm_q<V, CC>(t, 0);
+                    const int qk = L::template transpm_q<V, CC>(0, k);
+                    if ((qt & qk) || (qt | qk) != L::template transpm_q<V, CC>(t, k))
+                        ms.fail("merged lane order not a bit permutation");
+                    const int o = V * (qt | qk) + u;
+                    if (((o >> CC) & (NV - 1)) != k) ms.fail("merged vectors do not span the low run bits");
+                    const int64_t g = L::template transp_goff<CC>(o, rsv);
+                    if (L::template transp_goff<CC>(V * qt, rsv) + L::template transp_goff<CC>(V * qk, rsv) + u != g)
+                        ms.fail("merged global split");
+                    const int hl = e >> L1, lo = e & ((1 << L1) - 1);
+                    if (g != ((int64_t)cbrev((uint32_t)lo, L1) << rsv) + hl) ms.fail("merged target");
+                    gseen.insert(g);
+                }
+        for (int e = 0; e < N; ++e)
+            if (seen[e] != 1) { ms.fail("merged map not bijective"); break; }
+        if ((int)gseen.size() != N) ms.fail("merged global map not injective");
+        for (int w = 0; w < NT / 64; ++w)
+            for (int k = 0; k < NV; ++k)
+                for (int u = 0; u < V; ++u) {
+                    std::vector<int> a;
+                    for (int l = 0; l < 64; ++l)
+                        a.push_back(L::pad(L::template transpm_e<V, CC>(64 * w + l, k, u)));
+                    bank_account(ms, a);
+                }
+        std::snprintf(buf, sizeof buf,
+                      ", {\"K\": %d, \"LR\": %d, \"V\": %d, \"rows_log2\": %d, \"phase\": \"transposed_merged\", \"ok\": %s, \"ways64\": %d, \"ways32\": %d}",
+                      K, LR, V, CC, ms.ok ? "true" : "false", ms.worst64, ms.worst32);
+        out += buf;
+        if (!ms.ok) out += ", {\"error\": \"" + ms.err + "\"}";
+    }
     return out;
 }
 

@@ -205,7 +205,7 @@ def test_layout_selfcheck():
     assert ok, [r for r in rep if not r.get("ok", True)]
     phases = {r["phase"] for r in rep if "phase" in r}
     assert phases == {"rounds", "rounds_from_bit", "contig", "paley", "paley_blocks_2^8..2^(K-1)",
-                      "transposed"}
+                      "transposed", "transposed_merged"}
     # single-pass 2^12 tiles with 2^5 registers: two rounds after the stages
     # on the loaded vectors, against three from bit 0
     pre = {(r["K"], r["LR"], r["B0"]): r["rounds"] for r in rep if r.get("phase", "").startswith("rounds")}
