@@ -776,23 +776,72 @@ struct Engine {
                            Vec<C>::encode(vals[k]));
     }
 
+    // ---- transposed gather of the adjoint first pass -------------------------
+    // Where the merged map applies (merge_ok), a thread's vectors differ in
+    // row-element bits L1 - nk .. L1 - 1 and the adjoint's first stages (those
+    // bits, in decreasing order) run on them right after the gather, before the
+    // LDS write; the rounds then start below them.  gather_q(t, k): vector index
+    // of thread t's k-th vector; the split gather_q(t, 0) | gather_q(0, k) holds.
+    template <int CC, bool BR>
+    static __device__ __forceinline__ int gather_q(int t, int k)
+    {
+        constexpr int V = Vec<C>::V;
+        if constexpr (merge_ok<CC, BR>()) return L::template transpm_q<V, CC>(t, k);
+        else return L::template transp_q<V, CC>(t + NT * k);
+    }
+    template <int CC, bool BR>
+    static __device__ __forceinline__ int gather_e(int t, int k, int u)
+    {
+        constexpr int V = Vec<C>::V;
+        if constexpr (merge_ok<CC, BR>()) return L::template transpm_e<V, CC>(t, k, u);
+        else return L::template transp_e<V, CC, BR>(t, k, u);
+    }
+    // stages the gather leaves to the register rounds: row-element bits below
+    template <int CC, bool BR>
+    static constexpr int gather_nst() { return K - CC - (merge_ok<CC, BR>() ? merge_stages<CC>() : 0); }
+
+    // the gathered vectors (decoded) -> merged stages -> LDS
+    template <int CC, bool BR>
+    static __device__ __forceinline__ void put_gather(C *lds, C (*vals)[Vec<C>::V], int t)
+    {
+        constexpr int V = Vec<C>::V, NV = N / (V * NT), L1 = K - CC;
+        if constexpr (merge_ok<CC, BR>()) {
+            constexpr int nk = merge_stages<CC>();
+            static_assert((1 << nk) == NV, "one vector per value of the merged bits");
+#pragma unroll
+            for (int b = L1 - 1; b >= L1 - nk; --b) {
+                const int kb = L1 - 1 - b;
+#pragma unroll
+                for (int k = 0; k < NV; ++k)
+                    if (!(k & (1 << kb))) {
+#pragma unroll
+                        for (int u = 0; u < V; ++u) {
+                            C x = vals[k][u], y = vals[k | (1 << kb)][u];
+                            vals[k][u] = x + y;
+                            vals[k | (1 << kb)][u] = x - y;
+                        }
+                    }
+            }
+        }
+        C *lb = lds + L::pad(gather_e<CC, BR>(t, 0, 0));
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int u = 0; u < V; ++u) lb[L::pad(gather_e<CC, BR>(0, k, u))] = vals[k][u];
+    }
+
     template <int CC, bool BR = true>
     static __device__ __forceinline__ void load_transp(C *lds, const C *src, int64_t base,
                                                        int h0, int rs, int t)
     {
         constexpr int V = Vec<C>::V, NV = N / (V * NT);
         static_assert(V <= (1 << CC), "a vector must stay inside one run");
-        C *lb = lds + L::pad(L::template transp_e<V, CC, BR>(t, 0, 0));
-        const C *s = src + base + h0 + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), rs);
+        const C *s = src + base + h0 + L::template transp_goff<CC>(V * gather_q<CC, BR>(t, 0), rs);
         C vals[NV][V];
 #pragma unroll
         for (int k = 0; k < NV; ++k)
-            vload<NT_INTER>(s + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(NT * k), rs), vals[k]);
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-#pragma unroll
-            for (int u = 0; u < V; ++u)
-                lb[L::pad(L::template transp_e<V, CC, BR>(0, k, u))] = vals[k][u];
+            vload<NT_INTER>(s + L::template transp_goff<CC>(V * gather_q<CC, BR>(0, k), rs), vals[k]);
+        put_gather<CC, BR>(lds, vals, t);
     }
 
     // ---- one work item -------------------------------------------------------
@@ -979,7 +1028,7 @@ struct Engine {
                 store_transp_merged<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
                 return;
             }
-            rounds<ADJ>(lds, K - CC, t);
+            rounds<ADJ>(lds, ADJ ? gather_nst<CC, BR>() : K - CC, t);
             if constexpr (!ADJ) store_transp<CC, BR>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
                                          first_signs<CC>(it, a));
@@ -1162,7 +1211,10 @@ struct Engine {
                                                            C *lds, int t)
     {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
-        rounds_down_to1<J - 1>(lds, K - CC, t);  // round r: stages L1 - 1 .. LR
+        if constexpr (merge_ok<CC, true>())  // stages L1 - 1 .. LR ran on the gathered vectors
+            static_assert(gather_nst<CC, true>() == LR, "the gather leaves stages LR - 1 .. 0");
+        else
+            rounds_down_to1<J - 1>(lds, K - CC, t);  // round r: stages L1 - 1 .. LR
         turn_round_adj(it, a, lds, t);
         rounds<true>(lds, it.bits - LR, t);      // round r - 1: stages bits - LR - 1 .. 0
         store_contig<NT_INTER, C>(lds, static_cast<C *>(a.inter2),
@@ -1285,10 +1337,10 @@ struct Engine {
             constexpr int CC = rows_of<KIND>();
             const C *base = static_cast<const C *>(a.inter) + first_base<CC>(it, a) + it.h0;
             const uint32_t toff =
-                (uint32_t)L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), it.rs);
+                (uint32_t)L::template transp_goff<CC>(V * gather_q<CC, true>(t, 0), it.rs);
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                const C *pk = base + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(NT * k), it.rs);
+                const C *pk = base + L::template transp_goff<CC>(V * gather_q<CC, true>(0, k), it.rs);
                 raw[k] = ld16<NT_INTER>(pk + toff);
             }
         } else {
@@ -1339,14 +1391,10 @@ struct Engine {
             }
         } else if constexpr (src_inter<ADJ, KIND>()) {
             constexpr int CC = rows_of<KIND>();
-            C *lb = lds + L::pad(L::template transp_e<V, CC>(t, 0, 0));
+            C vals[NV][V];
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                C vals[V];
-                Vec<C>::decode(raw[k], vals);
-#pragma unroll
-                for (int u = 0; u < V; ++u) lb[L::pad(L::template transp_e<V, CC>(0, k, u))] = vals[u];
-            }
+            for (int k = 0; k < NV; ++k) Vec<C>::decode(raw[k], vals[k]);
+            put_gather<CC, true>(lds, vals, t);
         } else {
             const int bits = it.bits;
             if (bits == K) {
