@@ -358,7 +358,7 @@ chw_status chw_launch_times(chw_plan_t plan, float *ms, int *n);
  * covered exactly once per pass (one single-pass tile, or one first-pass and
  * one last-pass tile), no tile leaves its signal or the workspace, launches of
  * the two passes are ordered, persistent whole-signal items fit the tile
- * sizes, prefetching launches hold only full tiles of one kind, and the
+ * sizes, prefetching launches hold only full 2^15-element tiles of one kind, and the
  * round-boundary tiles of signed multi-round calls cover every two-pass
  * signal exactly once.  CHW_OK, or
  * CHW_ERR_UNSUPPORTED with the reason in chw_last_error(). */
