@@ -34,7 +34,7 @@ def _layout(sizes):
     return np.array(offs, dtype=np.int64)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16", "i32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16", "i32", "f64"])
 def test_haar_forward_backward(dtype):
     t = gu.torch()
     sizes = [0, 1, 3, 5, 12, 13, 17, 25] if dtype in ("f32", "i32") else [0, 2, 6, 12, 14, 19]
