@@ -175,7 +175,8 @@ def configure(plan, args, x, y, ws, key="plan"):
     cfg = json.loads(args.plan_config) if args.plan_config else BENCH_CONFIG
     if "plan" in cfg or "ragged" in cfg:
         cfg = cfg.get(key, {})
-    for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk", "stream", "pipeline"):
+    for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk", "stream", "pipeline",
+              "turn", "adjoint"):
         if k in cfg:
             plan.set_option(k, int(cfg[k]))
 

@@ -348,7 +348,10 @@ class Plan:
         return self._call(load().chw_forward, x, out, workspace, stream, False)
 
     def backward(self, g, out=None, workspace=None, stream=None):
-        """out = H^T g for every signal (the reversed cascade of transposed factors)."""
+        """out = H^T g for every signal: the reversed cascade of transposed factors,
+        which in the dyadic order gives the forward's bits, so by default the
+        library runs the forward launches (option "adjoint" = 1: the synthesis
+        kernels)."""
         return self._call(load().chw_backward, g, out, workspace, stream, True)
 
     def autotune(self, x, out, workspace=None, iters=3, stream=None):
