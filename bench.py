@@ -176,7 +176,7 @@ def configure(plan, args, x, y, ws, key="plan"):
     if "plan" in cfg or "ragged" in cfg:
         cfg = cfg.get(key, {})
     for k in ("exec", "lr12", "lr15", "single15", "split_l1", "chunk", "stream", "pipeline",
-              "turn", "adjoint"):
+              "turn", "adjoint", "spread"):
         if k in cfg:
             plan.set_option(k, int(cfg[k]))
 

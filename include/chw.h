@@ -337,6 +337,9 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               tiles prefetches only when every tile is one 2^15-element
  *               signal and there are at least 1024 of them;
  *               0: one workgroup per tile.
+ *   "spread"    1 (default): single-pass signals of one size in 2^15-element
+ *               tiles that would fill fewer than 256 tiles go one or a few per
+ *               tile (partly filled tiles, more CUs busy); 0: packed.
  *   "adjoint"   0 (default): chw_backward of a dyadic-order plan runs the
  *               forward launches (same bits, see chw_backward); 1: the Haar
  *               synthesis kernels.

@@ -983,6 +983,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     else if (k == "pipeline" && (value == 0 || value == 1)) cfg.pipeline = (int)value;
     else if (k == "turn" && (value == 0 || value == 1)) cfg.turn = (int)value;
     else if (k == "adjoint" && (value == 0 || value == 1)) cfg.adjoint = (int)value;
+    else if (k == "spread" && (value == 0 || value == 1)) cfg.spread = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
     return rebuild(plan, cfg);
 }

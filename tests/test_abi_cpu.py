@@ -191,13 +191,33 @@ def test_packed_misaligned_signal_is_rejected():
 
 def test_planner_packs_small_signals():
     p = chw.Plan([10] * 64, dtype="f32")
+    p.set_option("spread", 0)
     d = p.describe()["plan"]
     assert d["items"] == 16 and d["list"] == 0      # 4 consecutive signals per tile
     # gaps force an offset list
     offs = np.arange(65, dtype=np.int64) * 2048
     p = chw.Plan([10] * 64, dtype="f32", offsets=offs)
+    p.set_option("spread", 0)
     d = p.describe()["plan"]
     assert d["items"] == 16 and d["list"] == 64
+    p.check()
+
+
+def test_planner_spreads_small_groups():
+    # a size group in 2^15-element tiles that would fill fewer than 256 tiles
+    # goes one or a few signals per tile (the default); large groups and
+    # 2^12-element tiles stay packed
+    for ms, items in (([10] * 64, 16), ([14] * 256, 256), ([13] * 600, 200), ([13] * 2000, 500),
+                      ([12] * 8192, 8192), ([13] * 8, 8),
+                      ([9] * 3 + [20] * 2, 1 + 64 + 512 + 64)):  # + round-boundary tiles
+        p = chw.Plan(ms, dtype="f32")
+        d = p.describe()["plan"]
+        assert d["config"]["spread"] == 1
+        assert d["items"] == items, (ms[:2], d["items"])
+        p.check()
+    p = chw.Plan([13] * 8, dtype="f32")
+    p.set_option("spread", 0)
+    assert p.describe()["plan"]["items"] == 2
 
 
 def test_layout_selfcheck():
@@ -315,7 +335,9 @@ def test_stream_plan_shape():
     assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [0]
     p.check()
     # full single-pass tiles of several signals prefetch only when forced
+    # (packed: without spreading, 8 signals of 2^13 fill two tiles)
     p = chw.Plan([13] * 8, dtype="bf16")
+    p.set_option("spread", 0)
     assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [0]
     p.set_option("stream", 2)
     assert [r["stream"] for r in p.describe()["plan"]["forward"]] == [1]

@@ -256,6 +256,7 @@ def test_stream_bitwise(dtype):
             for stream in (0, 2):
                 p = chw.Plan(sizes, dtype=dtype, norm="none" if dtype == "i32" else "ortho")
                 p.set_option("adjoint", 1)
+                p.set_option("spread", 0)  # full tiles of several 2^13 signals
                 p.set_option("lr12", lr)
                 p.set_option("lr15", lr)
                 p.set_option("stream", stream)

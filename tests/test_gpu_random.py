@@ -22,6 +22,7 @@ CHOICES = {
     "chunk": (0, 1 << 20),
     "pipeline": (0, 1),
     "adjoint": (0, 1),
+    "spread": (0, 1),
 }
 DTYPES = ("f32", "bf16", "f16", "i32", "f64")
 

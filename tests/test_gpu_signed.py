@@ -189,6 +189,7 @@ def test_signed_prefetching_tiles(mode):
         res = []
         for stream in (0, 2):
             p = chw.Plan(sizes, dtype="f32")
+            p.set_option("spread", 0)  # full tiles of several 2^13 signals
             p.set_option("stream", stream)
             nbits = (1 << max(sizes)) if mode == "shared" else p.extent
             s = _signs_dev(workloads.pack_sign_bits(workloads.sign_rounds(751, 2, nbits)))
