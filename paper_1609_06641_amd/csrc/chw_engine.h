@@ -1263,8 +1263,10 @@ struct Engine {
     // [0, lv), lv = log2 of its element count: stages 0 .. lv - 1 run on the
     // loaded vectors and the register rounds cover bits [lv, 12) -- two rounds
     // instead of three, one LDS round trip fewer.  Same stages, operands and
-    // order as the plain rounds, so the same bits.  (Other tile shapes keep
-    // their round count, so they load plainly.)
+    // order as the plain rounds, so the same bits.  (The forward round-boundary
+    // tiles do the same with their first two stages, see turn_pre; other tile
+    // shapes would keep their round count, so they load plainly.)
+
     // log2 of the elements of type T in one 16-byte vector
     template <typename T>
     static constexpr int pre_bits()
