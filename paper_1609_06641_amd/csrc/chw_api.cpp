@@ -325,10 +325,14 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         if (r.persistent) {
             e = v->launch_persistent(dim3(std::min(a.nitems, grid_cap(v->fn_persistent))), stream, a);
         } else if (r.stream >= 1 && r.stream <= 5) {
-            const void *fn = v->fn_stream[r.stream - 1];
-            if (!fn || !v->launch_stream[r.stream - 1])
-                return fail(CHW_ERR_UNSUPPORTED, "no prefetching kernel for %d-bit tiles", r.K);
-            e = v->launch_stream[r.stream - 1](dim3(std::min(a.nitems, grid_cap(fn))), stream, a);
+            const bool dy = order == ORDER_DYADIC;
+            const void *fn = dy ? v->fn_stream[r.stream - 1] : v->fn_stream_order[order - 1][r.stream - 1];
+            const ItemsLauncher lf = dy ? v->launch_stream[r.stream - 1]
+                                        : v->launch_stream_order[order - 1][r.stream - 1];
+            if (!fn || !lf)
+                return fail(CHW_ERR_UNSUPPORTED, "no prefetching kernel for %d-bit tiles in order %d",
+                            r.K, order);
+            e = lf(dim3(std::min(a.nitems, grid_cap(fn))), stream, a);
         } else if (order != ORDER_DYADIC) {
             e = v->launch_order[order - 1](dim3(a.nitems), stream, a);
         } else {

@@ -166,6 +166,7 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         const std::vector<LaunchRange> &L = dir ? p.adj : p.fwd;
         for (const LaunchRange &r : L) {
             if (r.stream != 0 && (r.persistent || r.K != 15 ||
+                                  (dir == 1 && p.cfg.order != ORDER_DYADIC) ||
                                   r.stream != stream_source(p.items, r.begin, r.end, r.K, dir == 1))) {
                 *err = "prefetching launch over items that are not full tiles of one kind";
                 return false;

@@ -96,10 +96,8 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
 {
     BuiltPlan p;
     p.cfg = cfg;
-    if (p.cfg.order != ORDER_DYADIC) {  // one workgroup per tile, one launch per pass
-        p.cfg.stream = 0;
-        if (p.cfg.exec == 2) throw std::invalid_argument("the persistent launch computes the dyadic order only");
-    }
+    if (p.cfg.order != ORDER_DYADIC && p.cfg.exec == 2)
+        throw std::invalid_argument("the persistent launch computes the dyadic order only");
     if (dt == DT_F64) {  // FP64 has only the 2^12-element, 32-register tile kernels
         p.cfg.lr12 = 5;
         p.cfg.single15 = 0;
@@ -403,8 +401,10 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
                 return 0;
             return s;
         };
+        // the adjoint of the other orders gathers by the order's map: one
+        // workgroup per tile
         for (LaunchRange &r : p.fwd) r.stream = form(r, false);
-        for (LaunchRange &r : p.adj) r.stream = form(r, true);
+        for (LaunchRange &r : p.adj) r.stream = p.cfg.order == ORDER_DYADIC ? form(r, true) : 0;
     }
     *out = std::move(p);
 }

@@ -27,6 +27,8 @@ struct ItemsVariant {
     const void *fn_stream[5];         // BLOCKS, FIRST_A, FIRST_B, LAST, FIRST_C
     ItemsLauncher launch_order[2];    // one workgroup per item, sequency and
                                       // natural coefficient order
+    ItemsLauncher launch_stream_order[2][5];  // forward prefetching forms of
+    const void *fn_stream_order[2][5];        // those orders (K = 15), by kind
     ItemsLauncher launch_turn;        // KIND_TURN items (K = 15), one workgroup
                                       // per item (forward or adjoint boundary)
     ItemsLauncher launch_turn_stream; // prefetching form (forward)

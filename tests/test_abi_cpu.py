@@ -420,11 +420,15 @@ def test_order_flags_and_plan_shape():
         d = p.describe()["plan"]
         assert d["config"]["order"] == code
         if code:
-            # one workgroup per tile; the natural order's last pass takes the
-            # larger tiles (longer runs of its transposed store)
-            assert d["config"]["stream"] == 0
-            assert all(r["stream"] == 0 for r in d["forward"] + d["backward"])
+            # the forward prefetches like the dyadic one (full 2^15-element
+            # tiles of one kind); the adjoint gathers by the order's map, one
+            # workgroup per tile
+            assert d["config"]["stream"] == 1
+            assert any(r["stream"] > 0 for r in d["forward"])
+            assert all(r["stream"] == 0 for r in d["backward"])
         if code == 2:
+            # the natural order's last pass takes the larger tiles (longer runs
+            # of its transposed store)
             assert d["splits"][0]["K2"] == 15
         p.check()
         with pytest.raises(chw.CHWError):

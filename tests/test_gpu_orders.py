@@ -100,3 +100,29 @@ def test_order_signed_rounds(order):
     w = p.backward(p.backward(xd, workspace=ws) * d[1], workspace=ws) * d[0]
     _sync()
     assert t.equal(y, v) and t.equal(g, w)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "i32"])
+@pytest.mark.parametrize("order", ["sequency", "natural"])
+def test_order_prefetching_bitwise(dtype, order):
+    # the forward prefetching kernels of the other orders (full 2^15-element
+    # tiles: single-pass 2^13 and 2^15 signals, first and last passes of
+    # 2^17 and 2^22 signals) against one workgroup per tile, bit for bit
+    t = gu.torch()
+    norm = "none" if dtype == "i32" else "ortho"
+    gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
+    for sizes in ([13] * 8, [15] * 2, [17] * 3, [22] * 2):
+        x = np.concatenate([gen(830 + i, 1, k).reshape(-1) for i, k in enumerate(sizes)])
+        xd = gu.dev_tensor(x, dtype)
+        outs = []
+        for stream in (0, 2):
+            p = chw.Plan(sizes, dtype=dtype, norm=norm, order=order)
+            p.set_option("spread", 0)
+            p.set_option("stream", stream)
+            d = p.describe()["plan"]
+            assert any(r["stream"] > 0 for r in d["forward"]) == bool(stream), sizes
+            assert all(r["stream"] == 0 for r in d["backward"])
+            ws = t.empty(max(p.workspace_size(), 16), dtype=t.uint8, device="cuda")
+            outs.append(p.forward(xd, workspace=ws))
+        _sync()
+        assert t.equal(outs[0], outs[1]), (order, sizes)
