@@ -336,7 +336,14 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               1 (default): the same, except that a launch of single-pass
  *               tiles prefetches only when every tile is one 2^15-element
  *               signal and there are at least 1024 of them;
- *               0: one workgroup per tile.
+ *               0: one workgroup per tile.  (The adjoint of the sequency and
+ *               natural orders always runs one workgroup per tile.)
+ *   "turn"      1 (default): signed calls of several rounds join round r's
+ *               last pass and round r + 1's first pass (forward; the other
+ *               way round for the adjoint) in one launch of round-boundary
+ *               tiles, where the plan qualifies (FP32 / int32, dyadic order,
+ *               first passes in 2^15-element tiles); 0: one launch pair per
+ *               round.
  *   "spread"    1 (default): single-pass signals of one size in 2^15-element
  *               tiles that would fill fewer than 256 tiles go one or a few per
  *               tile (partly filled tiles, more CUs busy); 0: packed.
