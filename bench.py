@@ -2,8 +2,8 @@
 
 Headline workload: 1024 float32 signals of 2^20 elements, orthonormal
 dyadic-ordered WHT (the size the metric is quoted on).  Beside it: the BF16
-ragged form (20000 signals, log2 sizes in [6, 20], 2^30 elements, one
-persistent graph-captured launch).
+ragged form (20000 signals, log2 sizes in [6, 20], 2^30 elements; one launch
+per pass and tile size, replayed as a HIP graph).
 
 A step is one whole transform of the batch (every pass), inputs resident in
 HBM.  The timed region is bracketed by device synchronizations; rank 0 (the
