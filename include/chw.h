@@ -344,9 +344,9 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               tiles, where the plan qualifies (FP32 / int32, dyadic order,
  *               first passes in 2^15-element tiles); 0: one launch pair per
  *               round.
- *   "spread"    1 (default): single-pass signals of one size in 2^15-element
- *               tiles that would fill fewer than 256 tiles go one or a few per
- *               tile (partly filled tiles, more CUs busy); 0: packed.
+ *   "spread"    1 (default): a launch of single-pass 2^15-element tiles that
+ *               would fill fewer than 256 tiles puts its signals one or a few
+ *               per tile (partly filled tiles, more CUs busy); 0: packed.
  *   "adjoint"   0 (default): chw_backward of a dyadic-order plan runs the
  *               forward launches (same bits, see chw_backward); 1: the Haar
  *               synthesis kernels.

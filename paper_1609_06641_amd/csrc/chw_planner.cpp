@@ -131,22 +131,34 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     }
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t a, int64_t b) { return ms[a] < ms[b]; });
+    // packed 2^15-element single-pass tiles of the launch (all sizes): only a
+    // launch that would fill fewer than kSpreadTiles of them spreads its groups
+    int64_t packed15 = 0;
+    for (size_t s = 0, g; s < order.size(); s = g) {
+        g = s;
+        while (g < order.size() && ms[order[g]] == ms[order[s]]) ++g;
+        if (ms[order[s]] > 12) {
+            const int64_t per = (int64_t)1 << (15 - ms[order[s]]);
+            packed15 += ((int64_t)(g - s) + per - 1) / per;
+        }
+    }
+    const bool spread15 = p.cfg.spread && !persistent && packed15 < kSpreadTiles;
     size_t group_end = 0;  // end of the current size group in `order`
     int per = 0;           // signals per tile in the current size group
     for (size_t s = 0; s < order.size();) {
         const int m = ms[order[s]];
         const int K = m <= 12 ? 12 : 15;
         if (s >= group_end) {
-            // a size group of 2^15-element tiles (one workgroup fills a CU)
-            // that would fill fewer tiles than there are CUs is spread over
-            // more, partly filled tiles, so that its launch occupies more CUs
+            // a launch of 2^15-element tiles (one workgroup fills a CU) that
+            // would fill fewer tiles than there are CUs spreads its size groups
+            // over more, partly filled tiles, so that it occupies more CUs
             // (256 x 2^13: 11.3 -> 9.7 us; 2^12-element tiles share CUs and
             // gain nothing)
             group_end = s;
             while (group_end < order.size() && ms[order[group_end]] == m) ++group_end;
             const int64_t nm = (int64_t)(group_end - s);
             per = 1 << (K - m);
-            if (p.cfg.spread && K == 15 && !persistent && (nm + per - 1) / per < kSpreadTiles)
+            if (spread15 && K == 15)
                 per = (int)std::min<int64_t>(per, std::max<int64_t>(1, (nm + kSpreadTiles - 1) / kSpreadTiles));
         }
         size_t e = s;

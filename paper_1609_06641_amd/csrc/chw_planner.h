@@ -35,10 +35,10 @@ struct PlanConfig {
                         // intermediate is read back soon after it is written
     int order = 0;      // coefficient order (Order): set from the plan's
                         // flags, not a tuning choice
-    int spread = 1;     // 1: a size group of single-pass signals in 2^15-element
-                        // tiles that would fill fewer than kSpreadTiles tiles
-                        // goes one or a few signals per tile (partly filled
-                        // tiles, more CUs busy)
+    int spread = 1;     // 1: a launch of single-pass 2^15-element tiles that
+                        // would fill fewer than kSpreadTiles tiles puts its
+                        // signals one or a few per tile (partly filled tiles,
+                        // more CUs busy)
     int adjoint = 0;    // chw_backward of a dyadic-order plan: 0 runs the
                         // forward launches (the Paley-ordered H is symmetric
                         // and the adjoint cascade adds the same operands in
@@ -73,9 +73,9 @@ struct LaunchRange {
 // form.
 constexpr int kStreamBlocksMin = 1024;
 
-// Single-pass signals of one size in 2^15-element tiles that would fill fewer
-// tiles than this (the CU count of the part) go one or a few per tile instead,
-// up to this many tiles.
+// A launch of single-pass 2^15-element tiles that would fill fewer tiles than
+// this (the CU count of the part) puts its signals one or a few per tile
+// instead, up to this many tiles per size.
 constexpr int kSpreadTiles = 256;
 
 // Prefetching form of a launch of items [begin, end): 0 when the items are not

@@ -218,6 +218,10 @@ def test_planner_spreads_small_groups():
     p = chw.Plan([13] * 8, dtype="f32")
     p.set_option("spread", 0)
     assert p.describe()["plan"]["items"] == 2
+    # the rule looks at the whole launch: groups of 2^13, 2^14 and 2^15 that
+    # are each small but together fill 256 tiles stay packed
+    ms = [13] * 400 + [14] * 200 + [15] * 60
+    assert chw.Plan(ms, dtype="f32").describe()["plan"]["items"] == 100 + 100 + 60
 
 
 def test_layout_selfcheck():
