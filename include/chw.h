@@ -80,7 +80,8 @@ typedef enum {
 enum {
     CHW_FLAG_GRAPH = 1u << 0,        /* capture the launches of a call in a
                                         hipGraph and replay it               */
-    CHW_FLAG_NO_AUTOTUNE = 1u << 1,  /* ignore the tuning cache              */
+    CHW_FLAG_NO_AUTOTUNE = 1u << 1,  /* neither start from nor record into the
+                                        tuning cache (see chw_tuning_load)    */
     CHW_FLAG_PERSISTENT = 1u << 2,   /* one persistent launch (exec 2)        */
     CHW_FLAG_MULTI_LAUNCH = 1u << 3, /* one launch per HBM pass              */
     /* Coefficient order of the output of chw_forward (and of the input of
@@ -350,6 +351,10 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *   "adjoint"   0 (default): chw_backward of a dyadic-order plan runs the
  *               forward launches (same bits, see chw_backward); 1: the Haar
  *               synthesis kernels.
+ *   "occupancy" 0 (default): the looping launches (the persistent kernel,
+ *               the prefetching kernels) run as many workgroups as can be
+ *               resident; 1 .. 32: at most that many per CU (grid = min(items,
+ *               occupancy x CUs)).  A tuning choice of the persistent form.
  *   "timing"    1: record a HIP event around every launch (instrumentation;
  *               may be toggled at any time; disables graph replay)
  * Unknown keys or values give CHW_ERR_INVALID_ARGUMENT; so does changing a
@@ -380,12 +385,43 @@ chw_status chw_plan_describe(chw_plan_t plan, char *buf, size_t len);
 
 /* Time the candidate configurations of this plan on the given buffers (y and
  * workspace are overwritten; x is read only unless x == y) and keep the
- * fastest.  `iters` timed repetitions per candidate.  The plan's own
+ * fastest.  `iters` timed repetitions per candidate.  The candidates vary the
+ * level split of the two HBM passes, the registers per thread of both tile
+ * sizes, one or two passes for 2^13..2^15 signals, the prefetching form,
+ * pipelined chunks, and the persistent launch with its workgroups per CU
+ * (option "occupancy"); a launch form fixed by the plan's flags
+ * (CHW_FLAG_PERSISTENT, CHW_FLAG_MULTI_LAUNCH) is kept.  The plan's own
  * configuration is timed first, and another replaces the best so far only
- * when it is more than 1% faster.  Every candidate computes
- * bitwise-identical results. */
+ * when it is more than 1% faster.  Candidates the planner cannot build are
+ * skipped.  Every candidate computes bitwise-identical results.  Unless the
+ * plan has CHW_FLAG_NO_AUTOTUNE, the winner is recorded in the tuning cache
+ * under the plan's key (chw_plan_describe reports it as "tuning_key"). */
 chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace,
                         void *stream, int iters);
+
+/*
+ * Tuning cache.  The process keeps the configurations chw_autotune found,
+ * keyed by the dtype, the coefficient order, the launch form fixed by the
+ * flags and the size mix of the batch (each log2 size present, with the bit
+ * length of its signal count).  chw_plan starts a plan from the entry of its
+ * key unless it is given CHW_FLAG_NO_AUTOTUNE (chw_plan_describe reports
+ * "tuned": 1 then); chw_plan_set_option overrides single choices as usual.
+ * An entry never changes the numbers, only which kernels compute them.
+ *
+ * chw_tuning_save writes every entry to the text file `path` (host string),
+ * one line per key: the key, then name=value for each tuned option (lr12,
+ * lr15, single15, split_l1, exec, chunk, stream, pipeline, spread,
+ * occupancy); `comment` (may be NULL) is written first as '#' lines.
+ * chw_tuning_load merges such a file into the cache: CHW_ERR_INVALID_ARGUMENT
+ * (nothing merged, the line in chw_last_error) when it cannot be read or a
+ * line is malformed (unknown or repeated option, value out of range, missing
+ * option).  chw_tuning_clear empties the cache; chw_tuning_count gives the
+ * number of entries.  All four are host-only and thread-safe.
+ */
+chw_status chw_tuning_save(const char *path, const char *comment);
+chw_status chw_tuning_load(const char *path);
+chw_status chw_tuning_clear(void);
+chw_status chw_tuning_count(size_t *n);
 
 /* Host-only consistency check of the tile kernels' index maps (no device
  * needed): runs the kernels' own layout formulas on the CPU for every compiled

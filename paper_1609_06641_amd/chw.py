@@ -56,6 +56,10 @@ SIGNATURES = {
     "chw_plan_haar_walsh": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int32,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
     "chw_layout_selfcheck": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+    "chw_tuning_save": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_char_p]),
+    "chw_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "chw_tuning_clear": (ctypes.c_int, []),
+    "chw_tuning_count": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t)]),
     "chw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "chw_last_error": (ctypes.c_char_p, []),
     "chw_version": (ctypes.c_char_p, []),
@@ -96,6 +100,27 @@ def version():
     return load().chw_version().decode()
 
 
+def tuning_save(path, comment=None):
+    """Write the process's tuning cache to a text file (chw_tuning_save)."""
+    _check(load().chw_tuning_save(os.fsencode(path), None if comment is None else comment.encode()))
+
+
+def tuning_load(path):
+    """Merge a tuning file into the process's cache (chw_tuning_load); plans
+    made afterwards without FLAG_NO_AUTOTUNE start from the matching entry."""
+    _check(load().chw_tuning_load(os.fsencode(path)))
+
+
+def tuning_clear():
+    _check(load().chw_tuning_clear())
+
+
+def tuning_count():
+    n = ctypes.c_size_t()
+    _check(load().chw_tuning_count(ctypes.byref(n)))
+    return int(n.value)
+
+
 def layout_selfcheck():
     """(ok, report) of the host-side check of the kernels' index maps."""
     buf = ctypes.create_string_buffer(1 << 20)
@@ -106,6 +131,14 @@ def layout_selfcheck():
 def _torch():
     import torch
     return torch
+
+
+def _stream_ptr(stream, device):
+    """hipStream_t of a torch stream, of a raw handle (int), or of the current
+    stream of `device` when None."""
+    if stream is None:
+        stream = _torch().cuda.current_stream(device)
+    return stream if isinstance(stream, int) else stream.cuda_stream
 
 
 _TORCH_DT = {"f32": "float32", "bf16": "bfloat16", "f16": "float16", "i32": "int32",
@@ -217,6 +250,25 @@ class Plan:
         if t.numel() < self.extent:
             raise ValueError("%s holds %d elements, the plan spans %d" % (name, t.numel(), self.extent))
 
+    def _check_workspace(self, workspace, x, need):
+        """A caller's workspace must hold `need` bytes, be contiguous and live
+        on x's device: the library cannot see a buffer's size, and a short one
+        would be written past its end."""
+        if workspace is None:
+            return None
+        torch = _torch()
+        if not isinstance(workspace, torch.Tensor):
+            raise TypeError("workspace must be a torch tensor")
+        if not workspace.is_contiguous():
+            raise ValueError("workspace must be contiguous")
+        if workspace.device != x.device:
+            raise ValueError("workspace is on device %s, the data on %s" % (workspace.device, x.device))
+        have = workspace.numel() * workspace.element_size()
+        if have < need:
+            raise ValueError("workspace holds %d bytes, this plan needs %d (workspace_size())"
+                             % (have, need))
+        return workspace
+
     def _workspace(self, device, needed):
         if not needed:
             return None
@@ -240,10 +292,10 @@ class Plan:
             need = self.workspace_size() > 0 and (adjoint or narrow or rounds > 1 or
                                                   out.data_ptr() == x.data_ptr())
             workspace = self._workspace(x.device, need)
+        else:
+            self._check_workspace(workspace, x, self.workspace_size())
         ws_ptr = None if workspace is None else workspace.data_ptr()
-        if stream is None:
-            stream = torch.cuda.current_stream(x.device)
-        sp = stream if isinstance(stream, int) else stream.cuda_stream
+        sp = _stream_ptr(stream, x.device)
         if signed is None:
             _check(fn(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()), _VP(ws_ptr), _VP(sp)))
         else:
@@ -259,6 +311,8 @@ class Plan:
             out = torch.empty_like(x)
         if workspace is None:
             workspace = self._workspace(x.device, self.workspace_size() > 0)
+        else:
+            self._check_workspace(workspace, x, self.workspace_size())
         return self._call(load().chw_haar_forward, x, out, workspace, stream, False)
 
     def haar_backward(self, g, out=None, workspace=None, stream=None):
@@ -268,6 +322,8 @@ class Plan:
             out = torch.empty_like(g)
         if workspace is None:
             workspace = self._workspace(g.device, self.workspace_size() > 0)
+        else:
+            self._check_workspace(workspace, g, self.workspace_size())
         return self._call(load().chw_haar_backward, g, out, workspace, stream, True)
 
     def sign_words(self, mode="shared"):
@@ -285,9 +341,7 @@ class Plan:
             dev = torch.device("cuda") if device is None else torch.device(device)
             out = torch.empty(max(need, 1), dtype=torch.int32, device=dev)
         self._sign_check(out, mode, rounds)
-        if stream is None:
-            stream = torch.cuda.current_stream(out.device)
-        sp = stream if isinstance(stream, int) else stream.cuda_stream
+        sp = _stream_ptr(stream, out.device)
         _check(load().chw_philox_signs(self.handle, SIGN_MODES[mode],
                                        ctypes.c_uint64(int(seed) & (2**64 - 1)), int(rounds),
                                        _VP(out.data_ptr()), _VP(sp)))
@@ -311,9 +365,9 @@ class Plan:
         if workspace is None:
             workspace = torch.empty(max(self.nodes_workspace_size(), 16), dtype=torch.uint8,
                                     device=x.device)
-        if stream is None:
-            stream = torch.cuda.current_stream(x.device)
-        sp = stream if isinstance(stream, int) else stream.cuda_stream
+        else:
+            self._check_workspace(workspace, x, self.nodes_workspace_size())
+        sp = _stream_ptr(stream, x.device)
         _check(load().chw_nodes_forward(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()),
                                         _VP(workspace.data_ptr()), int(chunk), _VP(sp)))
         return out
@@ -360,11 +414,11 @@ class Plan:
         self._tensor_check(out, "out")
         if workspace is None:
             workspace = self._workspace(x.device, self.workspace_size() > 0)
+        else:
+            self._check_workspace(workspace, x, self.workspace_size())
         ws_ptr = None if workspace is None else workspace.data_ptr()
-        if stream is None:
-            stream = torch.cuda.current_stream(x.device)
         _check(load().chw_autotune(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()),
-                                   _VP(ws_ptr), _VP(stream.cuda_stream), int(iters)))
+                                   _VP(ws_ptr), _VP(_stream_ptr(stream, x.device)), int(iters)))
 
     def close(self):
         if getattr(self, "_h", None) is not None:

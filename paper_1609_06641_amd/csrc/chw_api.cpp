@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cerrno>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -79,7 +81,8 @@ struct DeviceState {
     int32_t *tiny_m = nullptr;
     hipStream_t cap = nullptr;     // private stream for graph capture
     std::vector<GraphEntry> graphs;
-    std::map<const void *, int> grid_cap;  // resident workgroups per kernel
+    // per looping kernel: resident workgroups per CU, CUs of the device
+    std::map<const void *, std::pair<int, int>> grid_cap;
     std::vector<hipEvent_t> ev;    // per-launch timing events (option "timing")
     int ev_used = 0;               // events recorded by the last call
 
@@ -138,6 +141,7 @@ struct chw_plan_s {
     bool used = false;
     bool timing = false;       // record a HIP event around every launch
     int last_dev = -1;         // device of the last call (for timings)
+    bool tuned = false;        // configuration taken from the tuning cache
     bool haar_built = false;   // the Haar pyramid table (independent of tuning)
     HaarPlan haar;
     std::mutex mu;
@@ -145,6 +149,69 @@ struct chw_plan_s {
 };
 
 namespace {
+
+// ---- tuning cache ------------------------------------------------------------
+// Configurations found by chw_autotune, kept for the rest of the process (and
+// written to / read from text files by chw_tuning_save / chw_tuning_load).
+// A plan made without CHW_FLAG_NO_AUTOTUNE starts from the entry whose key
+// matches it.  The key holds what decides the tuned choices: the dtype, the
+// coefficient order, the launch form the flags fix, and the size mix (every
+// log2 size present with the bit length of its signal count, so batches of
+// the same sizes and similar counts share an entry).
+
+std::mutex g_tune_mu;
+std::map<std::string, PlanConfig> g_tune;
+
+std::string tuning_key(int dt, int order, uint32_t flags, const std::vector<int32_t> &ms)
+{
+    int64_t cnt[31] = {0};
+    for (int32_t m : ms)
+        if (m >= 0 && m <= 30) ++cnt[m];
+    std::string k = "dt" + std::to_string(dt) + "/order" + std::to_string(order) + "/form" +
+                    std::to_string((flags & CHW_FLAG_PERSISTENT) ? 2 :
+                                   (flags & CHW_FLAG_MULTI_LAUNCH) ? 1 : 0) + "/m";
+    for (int m = 0; m <= 30; ++m) {
+        if (!cnt[m]) continue;
+        int bl = 0;
+        for (int64_t c = cnt[m]; c; c >>= 1) ++bl;
+        k += "," + std::to_string(m) + ":" + std::to_string(bl);
+    }
+    return k;
+}
+
+// the tuned choices of a configuration (the others are the caller's)
+void copy_tunables(const PlanConfig &from, PlanConfig *to)
+{
+    to->lr12 = from.lr12;
+    to->lr15 = from.lr15;
+    to->single15 = from.single15;
+    to->split_l1 = from.split_l1;
+    to->exec = from.exec;
+    to->chunk = from.chunk;
+    to->stream = from.stream;
+    to->pipeline = from.pipeline;
+    to->spread = from.spread;
+    to->occupancy = from.occupancy;
+}
+
+struct TunableField {
+    const char *name;
+    int64_t lo, hi;
+    int64_t PlanConfig::*i64;
+    int PlanConfig::*i32;
+};
+const TunableField kTunables[] = {
+    {"lr12", 0, 6, nullptr, &PlanConfig::lr12},
+    {"lr15", 5, 6, nullptr, &PlanConfig::lr15},
+    {"single15", 0, 1, nullptr, &PlanConfig::single15},
+    {"split_l1", -1, 30, nullptr, &PlanConfig::split_l1},
+    {"exec", 0, 2, nullptr, &PlanConfig::exec},
+    {"chunk", 0, INT64_MAX, &PlanConfig::chunk, nullptr},
+    {"stream", 0, 2, nullptr, &PlanConfig::stream},
+    {"pipeline", 0, 1, nullptr, &PlanConfig::pipeline},
+    {"spread", 0, 1, nullptr, &PlanConfig::spread},
+    {"occupancy", 0, 32, nullptr, &PlanConfig::occupancy},
+};
 
 chw_status rebuild(chw_plan_t p, const PlanConfig &cfg)
 {
@@ -223,6 +290,26 @@ chw_status ensure_tables(chw_plan_t p, int dev, DeviceState **out)
     }
     *out = &ds;
     return CHW_OK;
+}
+
+// Grid of a looping kernel (persistent or prefetching): the workgroups that
+// can be resident at once, or `occupancy` per CU when the plan sets it lower.
+int looping_grid(DeviceState &ds, const void *fn, int nt, int occupancy, int nitems)
+{
+    std::pair<int, int> &cap = ds.grid_cap[fn];
+    if (cap.first == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) != hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        cap = {per_cu, std::max(1, cus)};
+    }
+    const int per = occupancy > 0 ? std::min(cap.first, occupancy) : cap.first;
+    return std::max(1, std::min(nitems, per * cap.second));
 }
 
 // Record timing event number `i` of this call (option "timing").
@@ -305,25 +392,10 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         a.items = ds.items + r.begin;
         a.nitems = r.end - r.begin;
         hipError_t e;
-        // resident workgroups of a looping kernel on this device
-        auto grid_cap = [&](const void *fn) {
-            int &cap = ds.grid_cap[fn];
-            if (cap == 0) {
-                int per_cu = 0, dev = 0;
-                (void)hipGetDevice(&dev);
-                hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, v->nt, 0);
-                if (oe != hipSuccess || per_cu < 1) {
-                    (void)hipGetLastError();
-                    per_cu = 1;
-                }
-                int cus = 0;
-                (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-                cap = per_cu * std::max(1, cus);
-            }
-            return cap;
-        };
+        const int occ = b.cfg.occupancy;
         if (r.persistent) {
-            e = v->launch_persistent(dim3(std::min(a.nitems, grid_cap(v->fn_persistent))), stream, a);
+            e = v->launch_persistent(dim3(looping_grid(ds, v->fn_persistent, v->nt, occ, a.nitems)),
+                                     stream, a);
         } else if (r.stream >= 1 && r.stream <= 5) {
             const bool dy = order == ORDER_DYADIC;
             const void *fn = dy ? v->fn_stream[r.stream - 1] : v->fn_stream_order[order - 1][r.stream - 1];
@@ -332,7 +404,7 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
             if (!fn || !lf)
                 return fail(CHW_ERR_UNSUPPORTED, "no prefetching kernel for %d-bit tiles in order %d",
                             r.K, order);
-            e = lf(dim3(std::min(a.nitems, grid_cap(fn))), stream, a);
+            e = lf(dim3(looping_grid(ds, fn, v->nt, occ, a.nitems)), stream, a);
         } else if (order != ORDER_DYADIC) {
             e = v->launch_order[order - 1](dim3(a.nitems), stream, a);
         } else {
@@ -393,19 +465,7 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int s
             }
         }
         if (sl && sfn) {
-            int &cap = ds.grid_cap[sfn];
-            if (cap == 0) {
-                int per_cu = 0, dev = 0, cus = 0;
-                (void)hipGetDevice(&dev);
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sfn, v->nt, 0) != hipSuccess ||
-                    per_cu < 1) {
-                    (void)hipGetLastError();
-                    per_cu = 1;
-                }
-                (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-                cap = per_cu * std::max(1, cus);
-            }
-            e = sl(dim3(std::min(a.nitems, cap)), stream, a);
+            e = sl(dim3(looping_grid(ds, sfn, v->nt, b.cfg.occupancy, a.nitems)), stream, a);
         } else {
             e = v->launch_turn(dim3(a.nitems), stream, a);
         }
@@ -662,8 +722,28 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
     if (flags & CHW_FLAG_PERSISTENT) cfg.exec = 2;
     if (flags & CHW_FLAG_ORDER_SEQUENCY) cfg.order = ORDER_SEQUENCY;
     if (flags & CHW_FLAG_ORDER_NATURAL) cfg.order = ORDER_NATURAL;
+    if (!(flags & CHW_FLAG_NO_AUTOTUNE)) {
+        bool hit = false;
+        PlanConfig tuned = cfg;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(tuning_key(dt, cfg.order, flags, p->m));
+            if (it != g_tune.end()) {
+                copy_tunables(it->second, &tuned);
+                hit = true;
+            }
+        }
+        // an entry the planner cannot take leaves the plan untuned
+        if (hit && rebuild(p, tuned) == CHW_OK) {
+            p->tuned = true;
+            t_last_error.clear();
+            *plan = p;
+            return CHW_OK;
+        }
+    }
     chw_status s = rebuild(p, cfg);
     if (s != CHW_OK) return bad(s);
+    t_last_error.clear();
     *plan = p;
     return CHW_OK;
 }
@@ -988,8 +1068,11 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
     else if (k == "turn" && (value == 0 || value == 1)) cfg.turn = (int)value;
     else if (k == "adjoint" && (value == 0 || value == 1)) cfg.adjoint = (int)value;
     else if (k == "spread" && (value == 0 || value == 1)) cfg.spread = (int)value;
+    else if (k == "occupancy" && value >= 0 && value <= 32) cfg.occupancy = (int)value;
     else return fail(CHW_ERR_INVALID_ARGUMENT, "unknown option %s = %lld", key, (long long)value);
-    return rebuild(plan, cfg);
+    const chw_status s = rebuild(plan, cfg);
+    if (s == CHW_OK) plan->tuned = false;  // the caller's choice now
+    return s;
 }
 
 chw_status chw_launch_times(chw_plan_t plan, float *ms, int *n)
@@ -1030,9 +1113,12 @@ chw_status chw_plan_describe(chw_plan_t plan, char *buf, size_t len)
     if (!plan || !buf || len == 0) return fail(CHW_ERR_INVALID_ARGUMENT, "NULL argument");
     std::lock_guard<std::mutex> lk(plan->mu);
     char head[256];
-    std::snprintf(head, sizeof head, "{\"batch\": %lld, \"dtype\": %d, \"norm\": %d, \"extent\": %lld, \"plan\": ",
-                  (long long)plan->batch, plan->dt, (int)plan->norm, (long long)plan->extent);
-    std::string s = head + describe_plan(plan->built) + "}";
+    std::snprintf(head, sizeof head, "{\"batch\": %lld, \"dtype\": %d, \"norm\": %d, \"extent\": %lld, "
+                  "\"tuned\": %d, \"plan\": ",
+                  (long long)plan->batch, plan->dt, (int)plan->norm, (long long)plan->extent,
+                  plan->tuned ? 1 : 0);
+    std::string s = head + describe_plan(plan->built) + ", \"tuning_key\": \"" +
+                    tuning_key(plan->dt, plan->cfg.order, plan->flags, plan->m) + "\"}";
     if (s.size() + 1 > len) return fail(CHW_ERR_INVALID_ARGUMENT, "buffer of %zu bytes too small (%zu needed)", len, s.size() + 1);
     std::memcpy(buf, s.c_str(), s.size() + 1);
     return CHW_OK;
@@ -1048,7 +1134,11 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
     chw_status s = device_check(&dev);
     if (s != CHW_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // candidate configurations
+    // candidate configurations; a launch form fixed by the plan's flags
+    // (CHW_FLAG_PERSISTENT: one persistent launch; CHW_FLAG_MULTI_LAUNCH: one
+    // launch per pass) is kept, the other choices are searched
+    const bool only_persistent = (plan->flags & CHW_FLAG_PERSISTENT) != 0;
+    const bool only_multi = (plan->flags & CHW_FLAG_MULTI_LAUNCH) != 0;
     std::vector<PlanConfig> cands;
     bool has15 = false, has_multi = false;
     int maxm = 0;
@@ -1066,44 +1156,56 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
                 if (m > 15 && !choose_split(m, plan->dt, l1, false, plan->cfg.order, false, &sp)) ok = false;
             if (ok) l1s.push_back(l1);
         }
-    const bool can_persist = maxm <= 21;
-    for (int lr12 : {5, 6})
-        for (int lr15 : {5, 6})
-            for (int s15 : {0, 1}) {
-                if (!has15 && s15 == 0) continue;
-                if (plan->dt == DT_F64 && (lr12 != 5 || lr15 != 5 || s15 != 1)) continue;
-                for (int l1 : l1s)
-                    for (int stream_mode : {0, 1, 2}) {
-                        PlanConfig c = plan->cfg;
-                        c.lr12 = lr12;
-                        c.lr15 = lr15;
-                        c.single15 = s15;
-                        c.split_l1 = l1;
-                        c.exec = 0;
-                        c.stream = stream_mode;
-                        cands.push_back(c);
-                    }
+    if (!only_persistent) {
+        for (int lr12 : {5, 6})
+            for (int lr15 : {5, 6})
+                for (int s15 : {0, 1}) {
+                    if (!has15 && s15 == 0) continue;
+                    if (plan->dt == DT_F64 && (lr12 != 5 || lr15 != 5 || s15 != 1)) continue;
+                    for (int l1 : l1s)
+                        for (int stream_mode : {0, 1, 2}) {
+                            PlanConfig c = plan->cfg;
+                            c.lr12 = lr12;
+                            c.lr15 = lr15;
+                            c.single15 = s15;
+                            c.split_l1 = l1;
+                            c.exec = 0;
+                            c.chunk = 0;
+                            c.pipeline = 0;
+                            c.stream = stream_mode;
+                            c.occupancy = 0;
+                            cands.push_back(c);
+                        }
+                }
+        // pipelined chunks of 8, 16 or 32 MiB-signals' worth of elements
+        if (has_multi && plan->cfg.order == ORDER_DYADIC)
+            for (int64_t ch : {(int64_t)1 << 23, (int64_t)1 << 24, (int64_t)1 << 25}) {
+                PlanConfig c = plan->cfg;
+                c.exec = 0;
+                c.split_l1 = -1;
+                c.chunk = ch;
+                c.pipeline = 1;
+                c.occupancy = 0;
+                cands.push_back(c);
             }
-    // pipelined chunks of 8, 16 or 32 MiB-signals' worth of elements
-    if (has_multi && plan->cfg.order == ORDER_DYADIC)
-        for (int64_t ch : {(int64_t)1 << 23, (int64_t)1 << 24, (int64_t)1 << 25}) {
-            PlanConfig c = plan->cfg;
-            c.exec = 0;
-            c.split_l1 = -1;
-            c.chunk = ch;
-            c.pipeline = 1;
-            cands.push_back(c);
-        }
+    }
+    // the persistent launch computes the dyadic order only (the planner
+    // refuses it for the others) and takes signals up to 2^21
+    const bool can_persist = maxm <= 21 && plan->cfg.order == ORDER_DYADIC && !only_multi;
     if (can_persist)
-        for (int lr12 : {5, 6}) {
-            PlanConfig c = plan->cfg;
-            c.lr12 = lr12;
-            c.exec = 2;
-            c.split_l1 = -1;
-            c.stream = 0;
-            if (plan->dt == DT_F64 && lr12 != 5) continue;
-            cands.push_back(c);
-        }
+        for (int lr12 : {5, 6})
+            for (int occ : {0, 1, 2, 4}) {
+                if (plan->dt == DT_F64 && lr12 != 5) continue;
+                PlanConfig c = plan->cfg;
+                c.lr12 = lr12;
+                c.exec = 2;
+                c.split_l1 = -1;
+                c.chunk = 0;
+                c.pipeline = 0;
+                c.stream = 0;
+                c.occupancy = occ;
+                cands.push_back(c);
+            }
     // the plan's own configuration first: another one replaces the best so far
     // only when it is more than 1% faster, so near-ties keep the default and
     // repeated tunings pick the same kernels
@@ -1115,10 +1217,14 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
     float best_ms = 1e30f;
     PlanConfig best = saved;
     const bool was_used = plan->used;
+    int timed = 0;
+    s = CHW_OK;
     for (const PlanConfig &c : cands) {
         {
+            // a candidate the planner cannot take is skipped; it does not
+            // decide the call's status
             std::lock_guard<std::mutex> lk(plan->mu);
-            if ((s = rebuild(plan, c)) != CHW_OK) continue;
+            if (rebuild(plan, c) != CHW_OK) continue;
         }
         if ((s = run(plan, 0, x, y, workspace, stream)) != CHW_OK) break;  // warm-up
         if (hipEventRecord(e0, st) != hipSuccess) { s = fail(CHW_ERR_HIP, "hipEventRecord"); break; }
@@ -1130,9 +1236,10 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
         }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        ++timed;
         if (log_enabled())
-            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d stream=%d chunk=%lld pipeline=%d: %.4f ms\n",
-                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, c.stream, (long long)c.chunk, c.pipeline, ms / iters);
+            std::fprintf(stderr, "[libchw] tune exec=%d lr12=%d lr15=%d single15=%d split_l1=%d stream=%d chunk=%lld pipeline=%d occupancy=%d: %.4f ms\n",
+                         c.exec, c.lr12, c.lr15, c.single15, c.split_l1, c.stream, (long long)c.chunk, c.pipeline, c.occupancy, ms / iters);
         if (ms < 0.99f * best_ms) {
             best_ms = ms;
             best = c;
@@ -1140,10 +1247,139 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (s == CHW_OK && timed == 0)
+        s = fail(CHW_ERR_UNSUPPORTED, "no candidate configuration could be planned");
     std::lock_guard<std::mutex> lk(plan->mu);
     chw_status s2 = rebuild(plan, s == CHW_OK ? best : saved);
     plan->used = was_used || s == CHW_OK;
+    if (s == CHW_OK && s2 == CHW_OK && !(plan->flags & CHW_FLAG_NO_AUTOTUNE)) {
+        std::lock_guard<std::mutex> tk(g_tune_mu);
+        PlanConfig entry;
+        copy_tunables(best, &entry);
+        g_tune[tuning_key(plan->dt, plan->cfg.order, plan->flags, plan->m)] = entry;
+        plan->tuned = true;
+    }
     return s != CHW_OK ? s : s2;
+}
+
+chw_status chw_tuning_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return CHW_OK;
+}
+
+chw_status chw_tuning_count(size_t *n)
+{
+    if (!n) return fail(CHW_ERR_INVALID_ARGUMENT, "n is NULL");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *n = g_tune.size();
+    return CHW_OK;
+}
+
+chw_status chw_tuning_save(const char *path, const char *comment)
+{
+    if (!path) return fail(CHW_ERR_INVALID_ARGUMENT, "path is NULL");
+    std::string text = "# libchw tuning cache (chw_tuning_save): key, then the tuned planner options\n";
+    if (comment) {
+        std::string line;
+        for (const char *c = comment;; ++c) {
+            if (*c == '\n' || *c == '\0') {
+                text += "# " + line + "\n";
+                line.clear();
+                if (*c == '\0') break;
+            } else {
+                line += *c;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : g_tune) {
+            text += kv.first;
+            for (const TunableField &f : kTunables) {
+                const long long v = f.i64 ? (long long)(kv.second.*f.i64) : (long long)(kv.second.*f.i32);
+                text += " " + std::string(f.name) + "=" + std::to_string(v);
+            }
+            text += "\n";
+        }
+    }
+    FILE *fp = std::fopen(path, "w");
+    if (!fp) return fail(CHW_ERR_INVALID_ARGUMENT, "cannot open %s for writing", path);
+    const size_t w = std::fwrite(text.data(), 1, text.size(), fp);
+    const int c = std::fclose(fp);
+    if (w != text.size() || c != 0) return fail(CHW_ERR_INVALID_ARGUMENT, "cannot write %s", path);
+    return CHW_OK;
+}
+
+chw_status chw_tuning_load(const char *path)
+{
+    if (!path) return fail(CHW_ERR_INVALID_ARGUMENT, "path is NULL");
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return fail(CHW_ERR_INVALID_ARGUMENT, "cannot open %s", path);
+    std::map<std::string, PlanConfig> found;
+    std::string line;
+    int lineno = 0;
+    chw_status s = CHW_OK;
+    auto parse = [&](const std::string &ln) -> bool {
+        size_t i = 0;
+        while (i < ln.size() && (ln[i] == ' ' || ln[i] == '\t' || ln[i] == '\r')) ++i;
+        if (i == ln.size() || ln[i] == '#') return true;
+        size_t j = i;
+        while (j < ln.size() && ln[j] != ' ' && ln[j] != '\t') ++j;
+        const std::string key = ln.substr(i, j - i);
+        PlanConfig cfg;
+        bool seen[sizeof kTunables / sizeof kTunables[0]] = {};
+        while (j < ln.size()) {
+            while (j < ln.size() && (ln[j] == ' ' || ln[j] == '\t' || ln[j] == '\r')) ++j;
+            if (j == ln.size()) break;
+            size_t e = j;
+            while (e < ln.size() && ln[e] != ' ' && ln[e] != '\t' && ln[e] != '\r') ++e;
+            const std::string tok = ln.substr(j, e - j);
+            j = e;
+            const size_t eq = tok.find('=');
+            if (eq == std::string::npos || eq == 0 || eq + 1 == tok.size()) return false;
+            const std::string name = tok.substr(0, eq), val = tok.substr(eq + 1);
+            char *endp = nullptr;
+            errno = 0;
+            const long long v = std::strtoll(val.c_str(), &endp, 10);
+            if (errno != 0 || !endp || *endp != '\0') return false;
+            size_t k = 0;
+            for (; k < sizeof kTunables / sizeof kTunables[0]; ++k)
+                if (name == kTunables[k].name) break;
+            if (k == sizeof kTunables / sizeof kTunables[0] || seen[k]) return false;
+            if (v < kTunables[k].lo || v > kTunables[k].hi) return false;
+            seen[k] = true;
+            if (kTunables[k].i64) cfg.*(kTunables[k].i64) = (int64_t)v;
+            else cfg.*(kTunables[k].i32) = (int)v;
+        }
+        for (bool b : seen)
+            if (!b) return false;
+        found[key] = cfg;
+        return true;
+    };
+    for (int ch = std::fgetc(fp);; ch = std::fgetc(fp)) {
+        if (ch == '\n' || ch == EOF) {
+            ++lineno;
+            if (!parse(line)) {
+                s = fail(CHW_ERR_INVALID_ARGUMENT, "%s:%d: malformed tuning entry", path, lineno);
+                break;
+            }
+            line.clear();
+            if (ch == EOF) break;
+        } else {
+            line += (char)ch;
+            if (line.size() > 4096) {
+                s = fail(CHW_ERR_INVALID_ARGUMENT, "%s:%d: line too long", path, lineno + 1);
+                break;
+            }
+        }
+    }
+    std::fclose(fp);
+    if (s != CHW_OK) return s;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : found) g_tune[kv.first] = kv.second;
+    return CHW_OK;
 }
 
 }  // extern "C"

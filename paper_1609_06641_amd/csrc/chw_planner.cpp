@@ -511,10 +511,10 @@ std::string describe_plan(const BuiltPlan &p)
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
                   "\"exec\": %d, \"chunk\": %lld, \"stream\": %d, \"pipeline\": %d, \"order\": %d, "
-                  "\"turn\": %d, \"adjoint\": %d, \"spread\": %d}, ",
+                  "\"turn\": %d, \"adjoint\": %d, \"spread\": %d, \"occupancy\": %d}, ",
                   p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec,
                   (long long)p.cfg.chunk, p.cfg.stream, p.cfg.pipeline, p.cfg.order, p.cfg.turn,
-                  p.cfg.adjoint, p.cfg.spread);
+                  p.cfg.adjoint, p.cfg.spread, p.cfg.occupancy);
     s += buf;
     s += "\"splits\": [";
     for (size_t i = 0; i < p.splits.size(); ++i) {

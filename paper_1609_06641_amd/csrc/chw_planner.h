@@ -53,6 +53,10 @@ struct PlanConfig {
                         // run the prefetching kernel (a workgroup loops over
                         // items and fetches the next tile while the current
                         // one runs; one such workgroup fills a CU's LDS)
+    int occupancy = 0;  // workgroups per CU of the looping launches (the
+                        // persistent kernel, the prefetching kernels): their
+                        // grid is min(items, occupancy x CUs); 0 = as many as
+                        // can be resident
 };
 
 // Items [begin, end) of the plan's table run in one launch of the tile kernel

@@ -55,3 +55,23 @@ def per_signal_rel(y_hat, y_ref, log2_sizes, offsets=None):
         n = 1 << int(k)
         out[i] = metrics.rel_l2(y_hat[o:o + n], y_ref[o:o + n])
     return out
+
+
+def rne_narrow(t32, dtype):
+    """float32 tensor -> bf16 / f16 by torch's round-to-nearest-even
+    conversion, done on the CPU (c10's software rounding, independent of the
+    kernels' converts)."""
+    tt = torch()
+    return t32.detach().to("cpu").to(getattr(tt, TORCH_DT[dtype]))
+
+
+def narrowing_mismatches(y_half, y32, dtype):
+    """Elements where a bf16 / f16 result differs, bit for bit, from the RNE
+    narrowing of the float32 result of the same stages: 0 when the narrowing
+    is round to nearest even."""
+    tt = torch()
+    want = rne_narrow(y32, dtype).view(tt.int16)
+    got = y_half.detach().to("cpu").view(tt.int16)
+    if got.shape != want.shape:
+        raise ValueError("shapes differ: %s vs %s" % (tuple(got.shape), tuple(want.shape)))
+    return int((got != want).sum())

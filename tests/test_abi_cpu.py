@@ -567,3 +567,105 @@ def test_adjoint_option():
     with pytest.raises(chw.CHWError):
         p.set_option("adjoint", 2)
     p.check()
+
+
+def test_caller_workspace_is_checked():
+    # a caller-supplied workspace too small, strided or on another device is
+    # rejected by the binding before any call (the library cannot see its size)
+    import torch
+    p = chw.Plan([16, 12], dtype="bf16")
+    need = p.workspace_size()
+    assert need > 0
+    x = torch.zeros(p.extent, dtype=torch.bfloat16)
+    ok = torch.empty(need, dtype=torch.uint8)
+    assert p._check_workspace(ok, x, need) is ok
+    assert p._check_workspace(None, x, need) is None
+    with pytest.raises(ValueError, match="needs"):
+        p._check_workspace(torch.empty(need - 1, dtype=torch.uint8), x, need)
+    with pytest.raises(ValueError, match="needs"):
+        p._check_workspace(torch.empty(need // 4 - 1, dtype=torch.float32), x, need)
+    with pytest.raises(ValueError, match="contiguous"):
+        p._check_workspace(torch.empty(2 * need, dtype=torch.uint8)[::2], x, need)
+    with pytest.raises(ValueError, match="device"):
+        p._check_workspace(torch.empty(need, dtype=torch.uint8, device="meta"), x, need)
+    with pytest.raises(TypeError):
+        p._check_workspace(np.empty(need, dtype=np.uint8), x, need)
+
+
+def test_stream_argument_forms():
+    assert chw._stream_ptr(0, None) == 0
+    assert chw._stream_ptr(12345, None) == 12345
+
+    class S:
+        cuda_stream = 777
+    assert chw._stream_ptr(S(), None) == 777
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    # a tuning file written by hand is loaded; plans of its key start from the
+    # entry unless made with FLAG_NO_AUTOTUNE; save writes it back
+    chw.tuning_clear()
+    assert chw.tuning_count() == 0
+    ks = [20] * 8 + [12] * 100
+    p0 = chw.Plan(ks, dtype="bf16")
+    key = p0.describe()["tuning_key"]
+    assert p0.describe()["tuned"] == 0
+    f = tmp_path / "t.txt"
+    f.write_text("# comment\n\n%s lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 "
+                 "stream=0 pipeline=0 spread=1 occupancy=3\n" % key)
+    chw.tuning_load(str(f))
+    assert chw.tuning_count() == 1
+    p1 = chw.Plan(ks, dtype="bf16")
+    d = p1.describe()
+    assert d["tuned"] == 1
+    c = d["plan"]["config"]
+    assert (c["lr12"], c["lr15"], c["split_l1"], c["stream"], c["occupancy"]) == (5, 6, 10, 0, 3)
+    assert all(sp["L1"] == 10 for sp in d["plan"]["splits"])
+    p2 = chw.Plan(ks, dtype="bf16", flags=chw.FLAG_NO_AUTOTUNE)
+    assert p2.describe()["tuned"] == 0
+    assert p2.describe()["plan"]["config"]["split_l1"] == -1
+    # another dtype, size mix or launch form has another key
+    assert chw.Plan(ks, dtype="f32").describe()["tuned"] == 0
+    assert chw.Plan(ks + [12] * 200, dtype="bf16").describe()["tuned"] == 0
+    assert chw.Plan(ks, dtype="bf16", persistent=True).describe()["tuned"] == 0
+    # an option set by the caller replaces the tuned choice
+    p1.set_option("lr15", 5)
+    assert p1.describe()["tuned"] == 0
+    g = tmp_path / "out.txt"
+    chw.tuning_save(str(g), comment="made by a test\nsecond line")
+    text = g.read_text()
+    assert "# made by a test" in text and "# second line" in text
+    assert key in text and "occupancy=3" in text
+    chw.tuning_clear()
+    chw.tuning_load(str(g))
+    assert chw.Plan(ks, dtype="bf16").describe()["tuned"] == 1
+    chw.tuning_clear()
+
+
+@pytest.mark.parametrize("line", [
+    "k lr12=5",                                                  # options missing
+    "k lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=99",
+    "k lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=1 bogus=1",
+    "k lr12=5 lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1",
+    "k lr12=x lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=1",
+    "k lr12= lr15=6",
+    "k =5",
+])
+def test_tuning_file_rejects_malformed_lines(tmp_path, line):
+    chw.tuning_clear()
+    f = tmp_path / "bad.txt"
+    f.write_text("# ok\n" + line + "\n")
+    with pytest.raises(chw.CHWError) as e:
+        chw.tuning_load(str(f))
+    assert e.value.name == "CHW_ERR_INVALID_ARGUMENT" and ":2:" in e.value.detail
+    assert chw.tuning_count() == 0
+    with pytest.raises(chw.CHWError):
+        chw.tuning_load(str(tmp_path / "missing.txt"))
+
+
+def test_occupancy_option():
+    p = chw.Plan([20] * 4, dtype="f32", persistent=True)
+    p.set_option("occupancy", 2)
+    assert p.describe()["plan"]["config"]["occupancy"] == 2
+    with pytest.raises(chw.CHWError):
+        p.set_option("occupancy", 33)

@@ -84,9 +84,7 @@ def test_ragged_full_dependency_queue():
     p.set_option("exec", 1)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("persistent", [False, True])
-def test_ragged_full(dtype, persistent):
+def _ragged_inputs(dtype):
     torch = gu.torch()
     ks = workloads.ragged_log2_sizes(4001)
     offs = workloads.packed_offsets(ks)
@@ -95,14 +93,10 @@ def test_ragged_full(dtype, persistent):
         xt = workloads.to_half_precision(xr, "bf16").cuda()
     else:
         xt = torch.from_numpy(xr).cuda()
-    plan = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=persistent)
-    ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device="cuda")
-    if dtype == "bf16" and persistent:
-        # the bench's ragged form: a persistent graph plan set to its options
-        for k, v in bench.BENCH_CONFIG["ragged"].items():
-            plan.set_option(k, v)
-    y = plan.forward(xt, workspace=ws)
-    torch.cuda.synchronize()
+    return ks, offs, xt
+
+
+def _ragged_check(ks, offs, xt, y, dtype, label):
     # every signal with m <= 12 against the oracle, plus 40 large ones
     rng = np.random.default_rng(5)
     small = np.nonzero(ks <= 12)[0]
@@ -115,13 +109,45 @@ def test_ragged_full(dtype, persistent):
     ref = gu.oracle_packed(xs, ks[sel], threads=16)
     rel = gu.per_signal_rel(ys, ref, ks[sel])
     tol = 1e-5 if dtype == "f32" else 4e-3
-    print("%s persistent=%s: max rel-L2 %.3e over %d signals" % (dtype, persistent, rel.max(), len(sel)))
+    print("%s: max rel-L2 %.3e over %d signals" % (label, rel.max(), len(sel)))
     assert rel.max() <= tol
     # Parseval on every signal (segment sums)
     seg = np.repeat(np.arange(len(ks)), np.left_shift(1, ks.astype(np.int64)))
     nx = np.sqrt(np.bincount(seg, weights=xin ** 2))
     ny = np.sqrt(np.bincount(seg, weights=yout ** 2))
     assert np.max(np.abs(ny - nx) / nx) <= (1e-5 if dtype == "f32" else 8e-3)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_ragged_full(dtype, persistent):
+    # the planner's own choices: one launch per pass (persistent=False), or
+    # the one persistent launch (exec 2) the flag selects; graph-replayed
+    torch = gu.torch()
+    ks, offs, xt = _ragged_inputs(dtype)
+    plan = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=persistent)
+    d = plan.describe()["plan"]
+    assert d["config"]["exec"] == (2 if persistent else 0)
+    if persistent:
+        assert all(r["persistent"] for r in d["forward"])
+    ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device="cuda")
+    y = plan.forward(xt, workspace=ws)
+    torch.cuda.synchronize()
+    _ragged_check(ks, offs, xt, y, dtype, "%s persistent=%s" % (dtype, persistent))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_ragged_full_bench_config(dtype):
+    # the launch configuration the benchmark times for the ragged form
+    torch = gu.torch()
+    ks, offs, xt = _ragged_inputs(dtype)
+    plan = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=True)
+    for k, v in bench.BENCH_CONFIG["ragged"].items():
+        plan.set_option(k, v)
+    ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device="cuda")
+    y = plan.forward(xt, workspace=ws)
+    torch.cuda.synchronize()
+    _ragged_check(ks, offs, xt, y, dtype, "%s bench config" % dtype)
 
 
 @pytest.mark.parametrize("m", [23, 25, 26, 27])

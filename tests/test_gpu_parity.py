@@ -423,6 +423,60 @@ def test_autotune_with_caller_sized_workspace():
     assert gu.per_signal_rel(gu.host_f64(y), ref, sizes).max() <= 1e-5
 
 
+@pytest.mark.parametrize("order", ["sequency", "natural"])
+def test_autotune_other_orders(order):
+    # the tuner skips the candidates the planner refuses for these orders
+    # (the persistent launch computes the dyadic order only) and still returns
+    # a tuned plan; its output matches the oracle in the plan's order
+    from oracle import orders
+    t = gu.torch()
+    sizes = [16, 16, 12, 9, 14]
+    x = np.concatenate([workloads.float_signals(960 + i, 1, k).reshape(-1)
+                        for i, k in enumerate(sizes)])
+    p = chw.Plan(sizes, dtype="f32", order=order, flags=chw.FLAG_NO_AUTOTUNE)
+    ws = t.empty(max(p.workspace_size(), 16), dtype=t.uint8, device="cuda")
+    xd = gu.dev_tensor(x, "f32")
+    y = t.empty_like(xd)
+    p.autotune(xd, y, workspace=ws, iters=1)
+    assert p.describe()["plan"]["config"]["exec"] == 0
+    p.forward(xd, out=y, workspace=ws)
+    _sync()
+    dy = gu.oracle_packed(x.astype(np.float64), sizes)
+    conv = orders.natural_from_dyadic if order == "natural" else orders.sequency_from_dyadic
+    bounds = np.concatenate([[0], np.cumsum([1 << k for k in sizes])])
+    ref = np.concatenate([conv(dy[a:b]) for a, b in zip(bounds[:-1], bounds[1:])])
+    assert gu.per_signal_rel(gu.host_f64(y), ref, sizes).max() <= 1e-5
+
+
+def test_autotune_records_the_tuning_cache(tmp_path):
+    # a tuned configuration is kept for the process: a new plan of the same
+    # key starts from it, and a saved file brings it back after a clear
+    t = gu.torch()
+    sizes = [17] * 6 + [11] * 40
+    x = np.concatenate([workloads.float_signals(970 + i, 1, k).reshape(-1)
+                        for i, k in enumerate(sizes)])
+    chw.tuning_clear()
+    p = chw.Plan(sizes, dtype="f32")
+    xd = gu.dev_tensor(x, "f32")
+    y = t.empty_like(xd)
+    p.autotune(xd, y, iters=1)
+    cfg = p.describe()["plan"]["config"]
+    assert chw.tuning_count() == 1
+    q = chw.Plan(sizes, dtype="f32")
+    assert q.describe()["tuned"] == 1 and q.describe()["plan"]["config"] == cfg
+    f = tmp_path / "tune.txt"
+    chw.tuning_save(str(f))
+    chw.tuning_clear()
+    chw.tuning_load(str(f))
+    r = chw.Plan(sizes, dtype="f32")
+    assert r.describe()["plan"]["config"] == cfg
+    yr = r.forward(xd)
+    _sync()
+    chw.tuning_clear()
+    ref = gu.oracle_packed(x.astype(np.float64), sizes)
+    assert gu.per_signal_rel(gu.host_f64(yr), ref, sizes).max() <= 1e-5
+
+
 def test_streams_concurrent():
     t = gu.torch()
     sizes = [18] * 2
