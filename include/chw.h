@@ -183,6 +183,34 @@ chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes);
 chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace,
                        void *stream);
 
+/*
+ * chw_forward_noalloc -- chw_forward for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same result, bit for bit, as chw_forward on the same
+ * plan; the intermediate between the two HBM passes lives in a static device
+ * array of the library (64 MiB per device, held from the first call on a
+ * device until the process ends) instead of a workspace argument.  The call
+ * performs no hipMalloc, hipFree, graph capture or event creation.
+ *
+ *   x, y     as chw_forward (device buffers owned by the caller).
+ *   stream   as chw_forward.
+ * Errors (as chw_forward, plus):
+ *   CHW_ERR_UNSUPPORTED  the plan's intermediate (4 bytes per element of its
+ *                        two-pass signals, 8 for CHW_F64) exceeds 64 MiB, i.e.
+ *                        more than 2^24 such elements (2^23 for CHW_F64);
+ *                        or the plan's work tables have not been uploaded to
+ *                        the current device yet (one chw_forward or
+ *                        chw_backward call on that device does it); or option
+ *                        "timing" is on.
+ * A plan with CHW_FLAG_GRAPH launches directly here (no replay).  Every call
+ * on one device shares that device's array: calls that overlap in time on
+ * one device (on different streams, or from several host threads without
+ * ordering) race on it and give wrong results.  The array's contents are
+ * whatever the last call left; each call writes every intermediate element
+ * before it reads it, so nothing needs clearing.
+ */
+chw_status chw_forward_noalloc(chw_plan_t plan, const void *x, void *y, void *stream);
+
 /* chw_backward -- y_i = H_{m_i}^T g_i: the adjoint of eq. (3), the transposed
  * factors in reverse order (Haar synthesis).  In the dyadic order H_m is
  * symmetric and the synthesis cascade adds the same pairs in the same order

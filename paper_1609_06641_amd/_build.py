@@ -32,6 +32,7 @@ SOURCES = [
     "chw_kernels_f64.hip",
     "chw_philox.hip",
     "chw_nodes.hip",
+    "chw_scratch.hip",
     "chw_registry.cpp",
     "chw_planner.cpp",
     "chw_api.cpp",

@@ -37,6 +37,7 @@ SIGNATURES = {
     "chw_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     "chw_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "chw_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "chw_forward_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "chw_plan_destroy": (ctypes.c_int, [_VP]),
     "chw_plan_set_option": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_int64]),
     "chw_plan_describe": (ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_size_t]),
@@ -400,6 +401,20 @@ class Plan:
     def forward(self, x, out=None, workspace=None, stream=None):
         """out = H x for every signal (H'x in the unnormalized form)."""
         return self._call(load().chw_forward, x, out, workspace, stream, False)
+
+    def forward_noalloc(self, x, out, stream=None):
+        """out = H x through chw_forward_noalloc: the intermediate lives in the
+        library's static device scratch, and the call allocates nothing.  `out`
+        is required (this method allocates nothing either); the plan's tables
+        must already be on the device (one forward/backward call there)."""
+        self._tensor_check(x, "input")
+        self._tensor_check(out, "out")
+        if out.device != x.device:
+            raise ValueError("out is on device %s, the input on %s" % (out.device, x.device))
+        sp = _stream_ptr(stream, x.device)
+        _check(load().chw_forward_noalloc(self.handle, _VP(x.data_ptr()), _VP(out.data_ptr()),
+                                          _VP(sp)))
+        return out
 
     def backward(self, g, out=None, workspace=None, stream=None):
         """out = H^T g for every signal: the reversed cascade of transposed factors,

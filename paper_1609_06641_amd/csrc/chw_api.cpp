@@ -18,6 +18,7 @@
 
 #include "chw.h"
 #include "chw_planner.h"
+#include "chw_scratch.h"
 #include "chw_types.h"
 #include "chw_variants.h"
 
@@ -792,6 +793,49 @@ chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes)
 chw_status chw_forward(chw_plan_t plan, const void *x, void *y, void *workspace, void *stream)
 {
     return run(plan, 0, x, y, workspace, stream);
+}
+
+chw_status chw_forward_noalloc(chw_plan_t plan, const void *x, void *y, void *stream_v)
+{
+    chw_plan_t p = plan;
+    if (!p) return fail(CHW_ERR_INVALID_ARGUMENT, "plan is NULL");
+    if (p->batch == 0 || p->extent == 0) return CHW_OK;
+    if (!x || !y) return fail(CHW_ERR_INVALID_ARGUMENT, "x and y must be device pointers");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u)
+        return fail(CHW_ERR_MISALIGNED, "x and y must be 16-byte aligned");
+    const size_t bytes = (size_t)p->extent * (size_t)elem_bytes(p->dt);
+    if (x != y && intervals_overlap(x, bytes, y, bytes))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "x and y overlap partially");
+    // the intermediate of the plan's current configuration goes to the static
+    // scratch; every other byte the call touches is the caller's
+    const size_t need = p->built.ws_elems * (size_t)compute_bytes(p->dt);
+    if (need > SCRATCH_BYTES)
+        return fail(CHW_ERR_UNSUPPORTED,
+                    "the plan's intermediate needs %zu bytes; the static scratch of "
+                    "chw_forward_noalloc holds %zu (use chw_forward with a workspace)",
+                    need, (size_t)SCRATCH_BYTES);
+    int dev = 0;
+    chw_status s = device_check(&dev);
+    if (s != CHW_OK) return s;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->timing)
+        return fail(CHW_ERR_UNSUPPORTED,
+                    "option \"timing\" creates events; chw_forward_noalloc records none");
+    auto it = p->dev.find(dev);
+    if (it == p->dev.end() || it->second.version != p->version)
+        return fail(CHW_ERR_UNSUPPORTED,
+                    "the plan's work tables are not on device %d yet (one chw_forward or "
+                    "chw_backward call on this device uploads them)", dev);
+    void *ws = nullptr;
+    if (need > 0) {
+        hipError_t e = scratch_address(dev, &ws);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch");
+    }
+    p->used = true;
+    p->last_dev = dev;
+    // launched directly (no graph capture, which would allocate)
+    return enqueue_rounds(p, it->second, 0, x, y, ws, ws, 0, static_cast<hipStream_t>(stream_v),
+                          SignArgs{});
 }
 
 chw_status chw_backward(chw_plan_t plan, const void *g, void *y, void *workspace, void *stream)

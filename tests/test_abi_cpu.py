@@ -112,6 +112,32 @@ def test_no_device_path():
     assert st == 5, lib.chw_last_error()
 
 
+def test_forward_noalloc_validation():
+    # argument checks of the entry point that keeps the intermediate in the
+    # library's static scratch; none of these touches the (fake) buffers
+    lib = chw.load()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.chw_forward_noalloc(None, fake, fake, None) == 1
+    p = chw.Plan([10, 10])
+    assert lib.chw_forward_noalloc(p.handle, None, fake, None) == 1
+    assert lib.chw_forward_noalloc(p.handle, ctypes.c_void_p((1 << 20) + 4), fake, None) == 3
+    # 2^25 two-pass FP32 elements: a 128 MiB intermediate, above the 64 MiB scratch
+    big = chw.Plan([20] * 32)
+    assert lib.chw_forward_noalloc(big.handle, fake, fake, None) == 2
+    assert "64" in lib.chw_last_error().decode() or "67108864" in lib.chw_last_error().decode()
+    # 2^24 two-pass elements fit exactly; single-pass plans need no scratch at all
+    fits = chw.Plan([20] * 16)
+    single = chw.Plan([15] * 4096)
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.chw_forward_noalloc(fits.handle, fake, fake, None) == 5
+        assert lib.chw_forward_noalloc(single.handle, fake, fake, None) == 5
+    # the empty plan is a no-op
+    st, h = _plan_raw([])
+    assert lib.chw_forward_noalloc(h, None, None, None) == 0
+    assert lib.chw_plan_destroy(h) == 0
+
+
 def test_describe_and_planner_properties():
     # uniform large signals: two passes, the split covers every level once
     p = chw.Plan([20] * 3, dtype="f32")
