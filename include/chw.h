@@ -52,7 +52,12 @@ typedef enum {
     CHW_BF16 = 1,
     CHW_F16 = 2,
     CHW_I32 = 3,
-    CHW_F64 = 4
+    CHW_F64 = 4,
+    /* Range markers (not types): they make every int32 value a valid
+       chw_dtype, so that a caller's out-of-range value reaches the argument
+       check (CHW_ERR_INVALID_ARGUMENT) instead of being undefined. */
+    CHW_DTYPE_MIN_ = -2147483647 - 1,
+    CHW_DTYPE_MAX_ = 2147483647
 } chw_dtype;
 
 /* CHW_ORTHONORMAL: y = H_m x (float types only).
@@ -62,7 +67,9 @@ typedef enum {
  * case for |x| <= 128 and n <= 2^22). */
 typedef enum {
     CHW_ORTHONORMAL = 0,
-    CHW_UNNORMALIZED = 1
+    CHW_UNNORMALIZED = 1,
+    CHW_NORM_MIN_ = -2147483647 - 1, /* range markers, as for chw_dtype */
+    CHW_NORM_MAX_ = 2147483647
 } chw_norm;
 
 typedef enum {
@@ -110,10 +117,12 @@ typedef enum {
     CHW_SIGNS_PER_ELEMENT = 0,  /* bit e of a round's words is the sign of
                                    element e of the buffers (e counts from
                                    element 0, gaps included)                */
-    CHW_SIGNS_SHARED = 1        /* bit j is the sign of element j of every
+    CHW_SIGNS_SHARED = 1,       /* bit j is the sign of element j of every
                                    signal (one diagonal shared by all
                                    signals; a signal of 2^m elements uses
                                    bits 0 .. 2^m - 1)                       */
+    CHW_SIGN_MODE_MIN_ = -2147483647 - 1, /* range markers, as for chw_dtype */
+    CHW_SIGN_MODE_MAX_ = 2147483647
 } chw_sign_mode;
 
 /*

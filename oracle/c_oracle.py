@@ -16,7 +16,24 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "chw_oracle.c")
 _LIB = os.path.join(_HERE, "liborc_chw.so")
+# ORC_CHW_LIBRARY names another build of the same source (the sanitizer build
+# of the host checks); it is loaded as it is, never rebuilt here
+_LIB_OVERRIDE = os.environ.get("ORC_CHW_LIBRARY")
 _lib = None
+
+
+def build_sanitized(path):
+    """Compile chw_oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    (clang, sharing the sanitizer runtime of the library's host build) into
+    `path`."""
+    clang = "/opt/rocm/llvm/bin/clang"
+    tmp = path + ".tmp%d" % os.getpid()
+    subprocess.check_call([clang, "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-pthread",
+                           "-fno-fast-math", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-shared-libsan",
+                           "-fno-omit-frame-pointer", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, path)
+    return path
 
 
 def build(force=False):
@@ -34,8 +51,11 @@ def build(force=False):
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build()
+            lib = ctypes.CDLL(_LIB)
         for name, ptr in (("orc_chw_batch_f64", ctypes.c_double),
                           ("orc_chw_batch_i64", ctypes.c_int64)):
             fn = getattr(lib, name)

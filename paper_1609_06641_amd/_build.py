@@ -41,13 +41,27 @@ SOURCES = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+# Host-side sanitizers (AddressSanitizer, UndefinedBehaviorSanitizer) for the
+# CPU checks of the planner, plan checker, layout self-check and argument
+# validation: every flag applies to the host compilation only (the device code
+# is built as usual, without them).
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+SAN_LIB = os.path.join(HERE, "libchw_san.so")
+SAN_DIR = os.path.join(HERE, "_build", "san")
+
+
+def _compile(src, sanitize=False):
+    out_dir = SAN_DIR if sanitize else BUILD_DIR
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE
     else:
         cmd += ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
+    if sanitize:
+        cmd += SANITIZE
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
@@ -75,5 +89,40 @@ def build(verbose=False, jobs=None):
     return LIB
 
 
+def build_sanitized(verbose=False, jobs=None):
+    """Host-only libchw_san.so with ASan and UBSan (see SANITIZE).  A Python
+    process loads it with the sanitizer runtime preloaded
+    (sanitizer_runtime()) and CHW_LIBRARY pointing at it."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    jobs = jobs or min(8, len(SOURCES))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, sanitize=True), SOURCES))
+    tmp = SAN_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+        "-shared-libsan", "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), res.stderr))
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print("built", SAN_LIB, file=sys.stderr)
+    return SAN_LIB
+
+
+def sanitizer_runtime():
+    """Path of the compiler's shared ASan runtime (to LD_PRELOAD into Python)."""
+    res = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = res.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        res = subprocess.run([HIPCC, "--print-runtime-dir"], capture_output=True, text=True)
+        path = os.path.join(res.stdout.strip(), "libclang_rt.asan-x86_64.so")
+    return path
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "sanitize":
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)

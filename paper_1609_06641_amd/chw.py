@@ -11,7 +11,9 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libchw.so")
+# CHW_LIBRARY names another build of the library (the host-sanitizer build
+# the CPU checks load); by default the in-tree libchw.so
+LIB_PATH = os.environ.get("CHW_LIBRARY") or os.path.join(HERE, "libchw.so")
 
 # enums of chw.h
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "i32": 3, "f64": 4}
