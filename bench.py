@@ -228,7 +228,7 @@ def cpu_baseline(x_host, m, sample):
     c_oracle.chw_rows(xs[:one], threads=1)
     dt1 = time.perf_counter() - t0
     return {"value": round(sample * (1 << m) / dt / 1e9, 5), "unit": "Gelem/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "kind": "oracle", "cpu": cpu_model(),
             "sample": "%d of the %d signals of 2^%d, float64 plain-C cascade, %.2f s"
                       % (sample, x_host.shape[0], m, dt),
             "single_thread": {"value": round(one * (1 << m) / dt1 / 1e9, 5),
@@ -359,7 +359,11 @@ def bench_forms(args, x, y, m, batch, stream):
     return res
 
 
-def bench_ragged_bf16(args, dev, stream):
+def bench_ragged(args, dev, stream, dtype):
+    """The ragged workload (20000 signals, log2 sizes in [6, 20], 2^30
+    elements) in `dtype`: the configuration the autotuner picks among every
+    launch form, replayed as a HIP graph (the reported value), and beside it
+    the one-launch persistent form, autotuned within that form."""
     import torch
     import workloads
     from oracle import c_oracle, metrics
@@ -367,35 +371,63 @@ def bench_ragged_bf16(args, dev, stream):
     ks = workloads.ragged_log2_sizes(4001)
     offs = workloads.packed_offsets(ks)
     xr = workloads.ragged_values(4002, ks, offs)
-    xb = workloads.to_half_precision(xr, "bf16").to(dev)
+    if dtype == "f32":
+        xb = torch.from_numpy(xr).to(dev)
+    else:
+        xb = workloads.to_half_precision(xr, dtype).to(dev)
+    del xr
     yb = torch.empty_like(xb)
-    rp = chw.Plan(ks, dtype="bf16", offsets=offs, graph=True, persistent=True)
-    ws = torch.empty(max(rp.workspace_size(), 16), dtype=torch.uint8, device=dev)
-    configure(rp, args, xb, yb, ws, key="ragged")
-    rf = lambda: rp.forward(xb, out=yb, workspace=ws)  # noqa: E731
-    rms = time_steps(rf, args.steps, args.warmup, stream)
     relems = int(offs[-1])
-    launches = launch_breakdown(rp, rf, args.steps) if not args.no_launch_timing else [rms]
-    rp.forward(xb, out=yb, workspace=ws)   # graph replay again after timing
+    es = xb.element_size()
+    ws = torch.empty(max(chw.Plan(ks, dtype=dtype, offsets=offs).workspace_size(), 16),
+                     dtype=torch.uint8, device=dev)
+    tuned = not args.plan_config
+
+    def timed(plan, key):
+        if args.plan_config:
+            configure(plan, args, xb, yb, ws, key=key)
+        else:
+            plan.autotune(xb, yb, workspace=ws, iters=2)
+        fn = lambda: plan.forward(xb, out=yb, workspace=ws)  # noqa: E731
+        ms = time_steps(fn, args.steps, args.warmup, stream)
+        launches = launch_breakdown(plan, fn, args.steps) if not args.no_launch_timing else [ms]
+        fn()   # graph replay again after the timed launches
+        return ms, launches
+
+    rp = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True)
+    rms, launches = timed(rp, "ragged")
     torch.cuda.synchronize()
     # parity: a few signals of each size class
     sel = [int(np.nonzero(ks == k)[0][0]) for k in (6, 12, 16, 20)]
-    xin = xb.double().cpu().numpy()
-    yout = yb.double().cpu().numpy()
     rels = []
     for i in sel:
         n = 1 << int(ks[i])
-        ref = c_oracle.chw_batch(xin[offs[i]:offs[i] + n], [int(ks[i])])
-        rels.append(float(metrics.rel_l2(yout[offs[i]:offs[i] + n], ref)))
+        o = int(offs[i])
+        ref = c_oracle.chw_batch(xb[o:o + n].double().cpu().numpy(), [int(ks[i])])
+        rels.append(float(metrics.rel_l2(yb[o:o + n].double().cpu().numpy(), ref)))
     d = rp.describe()["plan"]
+    dt_code = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
+    profile = stored_profile(PROFILE_RAGGED, d["splits"]) if dtype == "bf16" else None
     res = {"value": round(relems / (rms / 1e3) / 1e9, 3), "unit": "Gelem/s",
            "ms_per_step": round(rms, 4), "signals": len(ks), "elements": relems,
-           "dtype": "bf16 storage, fp32 compute", "plan": d["config"],
+           "dtype": "%s storage, fp32 compute" % dtype if dtype != "f32" else "f32",
+           "plan": d["config"], "autotuned": tuned, "graph": True,
            "launches_per_call": len(d["forward"]),
-           "roofline": roofline(4, launches, plan_launches(rp, 1),
-                                stored_profile(PROFILE_RAGGED, d["splits"]), relems),
+           "roofline": roofline(2 * es, launches, plan_launches(rp, dt_code), profile, relems),
            "parity": {"log2_sizes": [int(ks[i]) for i in sel], "max_rel_l2": max(rels)}}
-    log("bf16 ragged: %.3f ms/step" % rms)
+    rp.close()
+    log("%s ragged: %.3f ms/step (%d launches)" % (dtype, rms, res["launches_per_call"]))
+    # the one persistent launch per call (exec 2), autotuned within that form
+    pp = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=True)
+    pms, plaunch = timed(pp, "persistent")
+    pd = pp.describe()["plan"]
+    res["one_launch"] = {"ms_per_step": round(pms, 4),
+                         "Gelem_s": round(relems / (pms / 1e3) / 1e9, 3),
+                         "plan": pd["config"], "autotuned": tuned,
+                         "launches_per_call": len(pd["forward"]),
+                         "launch_ms": [round(t, 4) for t in plaunch]}
+    pp.close()
+    log("%s ragged, one launch: %.3f ms/step" % (dtype, pms))
     del xb, yb, ws
     torch.cuda.empty_cache()
     return res
@@ -482,6 +514,265 @@ def run_other(args, dev, stream):
     if args.copy_gib > 0:
         out["copy_calibration"] = copy_calibration(args.copy_gib, dev, stream, args.steps)
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# every configuration of the workload list, cold and warm
+
+CONFIG_WORKLOADS = ("plain_small_f32", "plain_small_i32", "plain_2p24_f32", "precision_bf16",
+                    "precision_f16", "diff_f32")
+# A cold run cycles through copies of its buffers spanning at least this many
+# bytes, so that no step finds its data in the 256 MB memory-side cache left
+# there by the step before.
+ROTATE_BYTES = 1 << 30
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _time_oracle(fn):
+    t0 = time.perf_counter()
+    r = fn()
+    return r, time.perf_counter() - t0
+
+
+def _uniform_inputs(w):
+    import workloads
+    m = w.log2_sizes[0]
+    if w.dtype in ("bf16", "f16"):
+        return workloads.outlier_signals(w.seed, w.batch, m)
+    if w.dtype == "i32":
+        return workloads.int_signals(w.seed, w.batch, m)
+    return workloads.float_signals(w.seed, w.batch, m)
+
+
+class Rotation:
+    """`copies` device copies of an input (and room for as many outputs),
+    cycled one per call, so a cold step reads data the previous steps did not
+    leave in the caches."""
+
+    def __init__(self, x, copies):
+        import torch
+        self.n = x.numel()
+        self.copies = copies
+        self.xs = torch.empty(copies * self.n, dtype=x.dtype, device=x.device)
+        for r in range(copies):
+            self.xs[r * self.n:(r + 1) * self.n].copy_(x)
+        self.ys = torch.empty_like(self.xs)
+        self.i = 0
+
+    def next(self):
+        r = self.i % self.copies
+        self.i += 1
+        return self.xs[r * self.n:(r + 1) * self.n], self.ys[r * self.n:(r + 1) * self.n]
+
+    def first(self):
+        return self.xs[:self.n], self.ys[:self.n]
+
+
+def _copies(nbytes_per_set):
+    return max(1, -(-ROTATE_BYTES // max(1, nbytes_per_set)))
+
+
+def _step_figures(elems, bpe, cold_ms, warm_ms, launches, ls):
+    return {"ms_per_step": round(cold_ms, 5), "warm_ms_per_step": round(warm_ms, 5),
+            "Gelem_s": round(elems / (cold_ms / 1e3) / 1e9, 2),
+            "warm_Gelem_s": round(elems / (warm_ms / 1e3) / 1e9, 2),
+            "roofline": roofline(bpe, launches, ls, None, elems)}
+
+
+def bench_uniform_config(args, name, dev, stream):
+    """One uniform batch of the workload list: cold (rotating buffers) and warm
+    step times, per-launch roofline (cold), sampled parity and the oracle on
+    the host's cores."""
+    import torch
+    import workloads
+    from oracle import c_oracle, metrics
+    from paper_1609_06641_amd import chw
+    w = workloads.CONFIGS[name]
+    m, batch = w.log2_sizes[0], w.batch
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16,
+           "i32": torch.int32}[w.dtype]
+    xh = _uniform_inputs(w)
+    if w.dtype in ("bf16", "f16"):
+        xd = workloads.to_half_precision(xh, w.dtype).reshape(-1)
+    else:
+        xd = torch.from_numpy(xh.reshape(-1))
+    x = xd.to(tdt).to(dev)
+    elems = batch << m
+    es = x.element_size()
+    plan = chw.Plan([m] * batch, dtype=w.dtype, norm=w.norm)
+    ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device=dev)
+    rot = Rotation(x, _copies(2 * elems * es))
+    steps = args.steps
+
+    def cold():
+        a, b = rot.next()
+        plan.forward(a, out=b, workspace=ws)
+    x0, y0 = rot.first()
+    cold_ms = time_steps(cold, steps, args.warmup + rot.copies, stream)
+    warm_ms = time_steps(lambda: plan.forward(x0, out=y0, workspace=ws), steps, args.warmup, stream)
+    launches = launch_breakdown(plan, cold, steps) if not args.no_launch_timing else [cold_ms]
+    dt_code = {"f32": 0, "bf16": 1, "f16": 2, "i32": 3}[w.dtype]
+    res = {"workload": w.note, "dtype": w.dtype, "elements": elems,
+           "copies_rotated": rot.copies, "splits": plan.describe()["plan"]["splits"]}
+    res.update(_step_figures(elems, 2 * es, cold_ms, warm_ms, launches,
+                             plan_launches(plan, dt_code)))
+    res["device_ms_per_step"] = round(float(sum(launches)), 5)
+    res["forward_calls"] = (args.warmup + rot.copies + steps) + (args.warmup + steps) + \
+        (0 if args.no_launch_timing else steps) + 1
+    # parity on sampled signals, and the oracle timed on the host
+    plan.forward(x0, out=y0, workspace=ws)
+    torch.cuda.synchronize()
+    idx = sorted({0, batch // 2, batch - 1})
+    n = 1 << m
+    got = y0.reshape(batch, n)[idx]
+    xin = x0.reshape(batch, n)[idx]
+    threads = len(os.sched_getaffinity(0))
+    if w.dtype == "i32":
+        ref = c_oracle.chw_rows(xin.cpu().numpy().astype(np.int64))
+        res["parity"] = {"sampled_signals": idx, "bit_exact": bool(np.array_equal(
+            got.cpu().numpy().astype(np.int64), ref.astype(np.int32).astype(np.int64)))}
+        full = xd.numpy().astype(np.int64).reshape(batch, n)
+    else:
+        ref = c_oracle.chw_rows(xin.double().cpu().numpy())
+        res["parity"] = {"sampled_signals": idx, "max_rel_l2": float(np.max(
+            metrics.rel_l2(got.double().cpu().numpy(), ref)))}
+        full = xd.double().numpy().reshape(batch, n) if w.dtype in ("bf16", "f16") else \
+            xh.astype(np.float64).reshape(batch, n)
+    # the oracle on at most 2^26 elements of the batch, all cores
+    take = max(1, min(batch, (1 << 26) >> m))
+    _, dt = _time_oracle(lambda: c_oracle.chw_rows(full[:take], threads=threads))
+    res["cpu_baseline"] = {"value": round(take * n / dt / 1e9, 5), "unit": "Gelem/s",
+                           "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+                           "sample": "%d of the %d signals of 2^%d, %s plain-C cascade, %.2f s"
+                                     % (take, batch, m, "int64" if w.dtype == "i32" else "float64", dt)}
+    plan.close()
+    del x, rot, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_diff_config(args, dev, stream):
+    """y = H D x at 256 x 2^14 FP32 with one shared random-sign diagonal D:
+    forward and adjoint through the fused signed kernels (the autograd
+    function's two calls), cold and warm, beside the same through torch's sign
+    multiply and the plain transform; then a whole autograd step."""
+    import torch
+    import workloads
+    from oracle import metrics, signed
+    from paper_1609_06641_amd import chw
+    w = workloads.CONFIGS["diff_f32"]
+    m, batch = w.log2_sizes[0], w.batch
+    n, elems = 1 << m, w.batch << w.log2_sizes[0]
+    xh = workloads.float_signals(w.seed, batch, m)
+    d = workloads.sign_diagonal(5002, n)
+    gh = workloads.float_signals(5003, batch, m)
+    words = workloads.pack_sign_bits(d.reshape(1, -1)).reshape(-1).view(np.int32)
+    signs = torch.from_numpy(words.copy()).to(dev)
+    plan = chw.Plan([m] * batch, dtype="f32")
+    x = torch.from_numpy(xh.reshape(-1)).to(dev)
+    g = torch.from_numpy(gh.reshape(-1)).to(dev)
+    rx = Rotation(x, _copies(4 * elems * 4))
+    rg = Rotation(g, rx.copies)
+    steps = args.steps
+
+    def fused(rot_x, rot_g):
+        a, ya = rot_x.next()
+        b, yb = rot_g.next()
+        plan.forward_signed(a, signs, "shared", 1, out=ya)
+        plan.backward_signed(b, signs, "shared", 1, out=yb)
+    dflat = torch.from_numpy(np.tile(d.astype(np.float32), batch)).to(dev)
+
+    def unfused(rot_x, rot_g):
+        a, ya = rot_x.next()
+        b, yb = rot_g.next()
+        plan.forward(a * dflat, out=ya)
+        torch.mul(plan.backward(b, out=yb), dflat, out=yb)
+    cold_ms = time_steps(lambda: fused(rx, rg), steps, args.warmup + rx.copies, stream)
+    one_x, one_g = Rotation(x, 1), Rotation(g, 1)
+    warm_ms = time_steps(lambda: fused(one_x, one_g), steps, args.warmup, stream)
+    unf_ms = time_steps(lambda: unfused(rx, rg), steps, args.warmup + rx.copies, stream)
+    plan.set_option("timing", 1)
+    acc = None
+    for _ in range(steps):
+        a, ya = rx.next()
+        plan.forward_signed(a, signs, "shared", 1, out=ya)
+        t = plan.launch_times()
+        b, yb = rg.next()
+        plan.backward_signed(b, signs, "shared", 1, out=yb)
+        t = t + plan.launch_times()
+        acc = np.array(t) if acc is None else acc + np.array(t)
+    plan.set_option("timing", 0)
+    launches = list(acc / steps)
+    ls = [dict(l, name="forward " + l["name"]) for l in plan_launches(plan, 0)] + \
+         [dict(l, name="adjoint " + l["name"]) for l in plan_launches(plan, 0, "backward")]
+    # elements through the transform: forward and adjoint each take the batch
+    res = {"workload": w.note, "dtype": "f32", "elements": elems,
+           "copies_rotated": rx.copies, "step": "forward + adjoint (fused signs)"}
+    res.update(_step_figures(2 * elems, 8, cold_ms, warm_ms, launches,
+                             [dict(l, elements=elems) for l in ls]))
+    res["device_ms_per_step"] = round(float(sum(launches)), 5)
+    res["unfused_ms_per_step"] = round(unf_ms, 5)
+    # forward + adjoint pairs of this run (for per-step counter totals)
+    res["forward_calls"] = 2 * (args.warmup + rx.copies + steps) + (args.warmup + steps) + \
+        steps + (args.warmup + steps) + 1
+    # a whole autograd step (host overhead of autograd included)
+    xr = x.clone().requires_grad_(True)
+
+    def ag():
+        y = chw.signed_transform(xr, plan, signs, "shared", 1)
+        y.backward(g)
+    res["autograd_ms_per_step"] = round(time_steps(ag, steps, args.warmup, stream), 5)
+    torch.cuda.synchronize()
+    y = chw.signed_transform(xr, plan, signs, "shared", 1)
+    xr.grad = None
+    y.backward(g)
+    torch.cuda.synchronize()
+    idx = [0, batch - 1]
+    yh = y.detach().double().cpu().numpy().reshape(batch, n)
+    gx = xr.grad.double().cpu().numpy().reshape(batch, n)
+    rel = max(float(metrics.rel_l2(yh[i], signed.signed_forward(xh[i].astype(np.float64), [d])))
+              for i in idx)
+    relb = max(float(metrics.rel_l2(gx[i], signed.signed_adjoint(gh[i].astype(np.float64), [d])))
+               for i in idx)
+    res["parity"] = {"sampled_signals": idx, "max_rel_l2_forward": rel,
+                     "max_rel_l2_gradient": relb}
+    threads = len(os.sched_getaffinity(0))
+    sizes = np.full(batch, m, dtype=np.int32)
+    dfull = np.tile(d.astype(np.float64), batch)
+    t0 = time.perf_counter()
+    signed.signed_batch(xh.reshape(-1).astype(np.float64), sizes, [dfull], threads=threads)
+    signed.signed_batch(gh.reshape(-1).astype(np.float64), sizes, [dfull], adjoint=True,
+                        threads=threads)
+    dt = time.perf_counter() - t0
+    res["cpu_baseline"] = {"value": round(2 * elems / dt / 1e9, 5), "unit": "Gelem/s",
+                           "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+                           "sample": "forward and adjoint of all %d signals of 2^%d, float64 "
+                                     "plain-C cascade with the sign flips, %.2f s" % (batch, m, dt)}
+    plan.close()
+    return res
+
+
+def bench_configs(args, dev, stream):
+    out = {}
+    for name in CONFIG_WORKLOADS:
+        t0 = time.perf_counter()
+        out[name] = bench_diff_config(args, dev, stream) if name == "diff_f32" else \
+            bench_uniform_config(args, name, dev, stream)
+        log("config %s: %.4f ms/step cold, %.4f warm (%.1f s)" % (
+            name, out[name]["ms_per_step"], out[name]["warm_ms_per_step"],
+            time.perf_counter() - t0))
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -628,6 +919,8 @@ def main():
     ap.add_argument("--plan-config", help="JSON planner options instead of autotuning")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations of the workload list")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other orders / Haar / signed forms on the headline batch")
     ap.add_argument("--no-launch-timing", action="store_true")
@@ -660,13 +953,24 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.workload in CONFIG_WORKLOADS:
+        # one configuration of the workload list, cold and warm (its own line)
+        res = bench_diff_config(args, dev, stream) if args.workload == "diff_f32" else \
+            bench_uniform_config(args, args.workload, dev, stream)
+        if args.copy_gib > 0:
+            res["copy_calibration"] = copy_calibration(args.copy_gib, dev, stream, args.steps)
+        print(json.dumps(res), flush=True)
+        return
     if args.workload != "plain_2p20_f32":
         run_other(args, dev, stream)
         return
     out = {}
     x_host, m = bench_headline(args, dev, stream, out)
     if not args.no_ragged:
-        out["bf16_ragged"] = bench_ragged_bf16(args, dev, stream)
+        out["bf16_ragged"] = bench_ragged(args, dev, stream, "bf16")
+        out["f32_ragged"] = bench_ragged(args, dev, stream, "f32")
+    if not args.no_configs:
+        out["configs"] = bench_configs(args, dev, stream)
     if args.copy_gib > 0:
         out["copy_calibration"] = copy_calibration(args.copy_gib, dev, stream, args.steps)
     if not args.no_cpu:
