@@ -274,11 +274,36 @@ struct Engine {
         }
     }
 
-    template <int j, bool ADJ, int B0 = 0>
-    static __device__ __forceinline__ void round(C *lds, int nst, int t)
+    // One register round with its first NA active stages known at compile
+    // time: read, NA stages, write.  Each count is a whole round of its own,
+    // so no value crosses a branch between the stages (a stage skipped at run
+    // time inside one round would make the compiler carry both register
+    // assignments and reconcile them with moves).
+    template <int j, bool ADJ, int B0, int NA>
+    static __device__ __forceinline__ void round_body(C *lds, int t)
+    {
+        constexpr int lo = L::flo(j, B0), a0 = L::alo(j, B0);
+        C *base = lds + L::pad(L::round_tbase(j, t, B0));
+        C v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = base[L::pad(L::round_reg(j, i, B0))];
+        if constexpr (!ADJ) {
+#pragma unroll
+            for (int bit = a0; bit < a0 + NA; ++bit) bfly(v, bit - lo);
+        } else {
+#pragma unroll
+            for (int bit = a0 + NA - 1; bit >= a0; --bit) bfly(v, bit - lo);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) base[L::pad(L::round_reg(j, i, B0))] = v[i];
+    }
+
+    // round j with each stage tested against nst: the form for a bound known
+    // at compile time (the tests fold away)
+    template <int j, bool ADJ, int B0>
+    static __device__ __forceinline__ void round_nst(C *lds, int nst, int t)
     {
         constexpr int lo = L::flo(j, B0), a0 = L::alo(j, B0), a1 = L::ahi(j, B0);
-        if (a0 >= nst) return;  // no active stage in this round (uniform)
         C *base = lds + L::pad(L::round_tbase(j, t, B0));
         C v[R];
 #pragma unroll
@@ -297,6 +322,38 @@ struct Engine {
         __syncthreads();
     }
 
+    // the active stages of round j are [a0, min(a1, nst)): dispatch their
+    // count (uniform) to a compile-time round
+    template <int j, bool ADJ, int B0, int NA>
+    static __device__ __forceinline__ void round_count(C *lds, int na, int t)
+    {
+        if constexpr (NA >= 1) {
+            if (na == NA) round_body<j, ADJ, B0, NA>(lds, t);
+            else round_count<j, ADJ, B0, NA - 1>(lds, na, t);
+        }
+    }
+
+    // 2^12-element tiles with 2^5 registers dispatch the stage count of a
+    // round to a compile-time round (VALU: with the stages tested one by one,
+    // the register moves that reconcile skipped and taken stages cost about a
+    // third as much as the butterflies).  The other shapes test the stages
+    // one by one: there the register allocator fits that form better (2^15
+    // tiles' prefetching forms run at the register limit; 2^6 registers would
+    // lose a wave per SIMD).
+    template <int j, bool ADJ, int B0 = 0>
+    static __device__ __forceinline__ void round(C *lds, int nst, int t)
+    {
+        constexpr int a0 = L::alo(j, B0), a1 = L::ahi(j, B0);
+        if (a0 >= nst) return;  // no active stage in this round (uniform)
+        if constexpr (K == 12 && LR == 5) {
+            if (nst >= a1) round_body<j, ADJ, B0, a1 - a0>(lds, t);
+            else round_count<j, ADJ, B0, a1 - a0 - 1>(lds, nst - a0, t);
+            __syncthreads();
+        } else {
+            round_nst<j, ADJ, B0>(lds, nst, t);
+        }
+    }
+
     // the stages [B0 + j LR, nst) (forward) or [0, nst) (adjoint, B0 = 0)
     template <bool ADJ, int j = 0, int B0 = 0>
     static __device__ __forceinline__ void rounds(C *lds, int nst, int t)
@@ -310,6 +367,26 @@ struct Engine {
                 round<J - 1 - j, true>(lds, nst, t);
                 rounds<true, j + 1>(lds, nst, t);
             }
+        }
+    }
+
+    // rounds() with the stage bound known at compile time
+    template <bool ADJ, int NST, int j = 0, int B0 = 0>
+    static __device__ __forceinline__ void rounds_ct(C *lds, int t)
+    {
+        static_assert(!ADJ || B0 == 0, "the adjoint rounds start at bit 0");
+        if constexpr (j < L::rounds_from(B0)) {
+            constexpr int jj = ADJ ? J - 1 - j : j;
+            constexpr int a0 = L::alo(jj, B0), a1 = L::ahi(jj, B0);
+            if constexpr (a0 < NST) {
+                if constexpr (K == 12 && LR == 5) {
+                    round_body<jj, ADJ, B0, (a1 < NST ? a1 : NST) - a0>(lds, t);
+                    __syncthreads();
+                } else {
+                    round_nst<jj, ADJ, B0>(lds, NST, t);
+                }
+            }
+            rounds_ct<ADJ, NST, j + 1, B0>(lds, t);
         }
     }
 
@@ -370,13 +447,11 @@ struct Engine {
     // vector holds every value of tile bits [0, PRE) of its block, and the
     // stages below min(PRE, pre_lim) run on it (after the signs) before it
     // goes to LDS.
-    template <int V, int PRE>
-    static __device__ __forceinline__ void pre_stages(C *v, int lim)
+    template <int V, int NB>
+    static __device__ __forceinline__ void pre_stages_n(C *v)
     {
-        static_assert((1 << PRE) <= V, "pre-stages stay inside one vector");
 #pragma unroll
-        for (int b = 0; b < PRE; ++b) {
-            if (b >= lim) break;  // uniform
+        for (int b = 0; b < NB; ++b) {
 #pragma unroll
             for (int i = 0; i < V; ++i)
                 if (!(i & (1 << b))) {
@@ -384,6 +459,20 @@ struct Engine {
                     v[i] = x + y;
                     v[i | (1 << b)] = x - y;
                 }
+        }
+    }
+    // stages 0 .. min(PRE, lim) - 1; the count (uniform) picks a
+    // compile-time sequence, as round() does
+    template <int V, int PRE>
+    static __device__ __forceinline__ void pre_stages(C *v, int lim)
+    {
+        static_assert((1 << PRE) <= V && PRE <= 3, "pre-stages stay inside one vector");
+        if constexpr (PRE >= 1) {
+            if (lim >= PRE) pre_stages_n<V, PRE>(v);
+            else if (lim == PRE - 1) pre_stages_n<V, PRE - 1>(v);
+            else if constexpr (PRE >= 3) {
+                if (lim == PRE - 2) pre_stages_n<V, PRE - 2>(v);
+            }
         }
     }
 
@@ -1024,11 +1113,11 @@ struct Engine {
         } else if constexpr (is_first_kind(KIND)) {
             constexpr int CC = rows_of<KIND>();
             if constexpr (!ADJ && merge_ok<CC, BR>()) {
-                rounds<false>(lds, K - CC - merge_stages<CC>(), t);
+                rounds_ct<false, K - CC - merge_stages<CC>()>(lds, t);
                 store_transp_merged<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
                 return;
             }
-            rounds<ADJ>(lds, ADJ ? gather_nst<CC, BR>() : K - CC, t);
+            rounds_ct<ADJ, ADJ ? gather_nst<CC, BR>() : K - CC>(lds, t);
             if constexpr (!ADJ) store_transp<CC, BR>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
             else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
                                          first_signs<CC>(it, a));
@@ -1127,7 +1216,7 @@ struct Engine {
             static_assert(K - CC - merge_stages<CC>() == LR, "stages 0 .. LR - 1 ran in turn_round0");
             store_transp_merged<CC>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
         } else {
-            rounds<false, 1>(lds, K - CC, t);
+            rounds_ct<false, K - CC, 1>(lds, t);
             store_transp<CC, true>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
         }
     }
