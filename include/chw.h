@@ -102,11 +102,19 @@ enum {
        order other than dyadic run one workgroup per tile (no prefetching)
        and one launch per round of a signed call. */
     CHW_FLAG_ORDER_SEQUENCY = 1u << 4,
-    CHW_FLAG_ORDER_NATURAL = 1u << 5
+    CHW_FLAG_ORDER_NATURAL = 1u << 5,
+    /* Run signals of 2^20 elements or more in the three HBM passes that
+       signals above 2^27 always take (see chw_workspace_size): the same
+       numbers, more traffic.  It exists to check that form at sizes an
+       oracle runs in seconds.  Dyadic order only; exclusive with
+       CHW_FLAG_PERSISTENT. */
+    CHW_FLAG_THREE_PASS = 1u << 6
 };
 
-/* Largest supported log2 signal size (all dtypes except F64). */
-#define CHW_MAX_LOG2 27
+/* Largest supported log2 signal size (all dtypes except F64).  Signals above
+ * 2^15 elements run in two HBM passes, signals above 2^27 in three (dyadic
+ * order only: the other orders stop at 2^27). */
+#define CHW_MAX_LOG2 30
 /* Largest supported log2 signal size for CHW_F64. */
 #define CHW_MAX_LOG2_F64 20
 /* Largest number of rounds of a signed call (chw_forward_signed). */
@@ -171,12 +179,14 @@ chw_status chw_plan_haar_walsh(chw_plan_t *plan, int64_t batch, int32_t m, chw_d
                                chw_norm norm, uint32_t flags);
 
 /* Bytes of device workspace a call may need: the FP32 (FP64 for CHW_F64)
- * intermediate between HBM passes of every signal larger than 2^12 elements.
+ * intermediate between HBM passes of every signal larger than 2^12 elements,
+ * twice over for the signals that take three passes (above 2^27, or 2^20 and
+ * above with CHW_FLAG_THREE_PASS), which keep two intermediates.
  * The figure does not depend on tuning or options, so a buffer sized from it
  * stays large enough after chw_autotune / chw_plan_set_option.  Calls whose
  * signals all run in one pass, and out-of-place forward F32/I32/F64 calls
- * (which route the intermediate through y), accept NULL.  A workspace must
- * not be shared by concurrent calls. */
+ * without three-pass signals (which route the intermediate through y), accept
+ * NULL.  A workspace must not be shared by concurrent calls. */
 chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes);
 
 /*

@@ -20,6 +20,8 @@ cascade_schedule  the list of Haar transforms the cascade applies.
 closed_form       entries of H_m from the popcount formula (independent).
 radix2_paley      textbook in-place radix-2 WHT (natural order) followed by
                   the bit-reversal permutation to dyadic order (independent).
+coefficient       one output y_i of H_m x from the popcount formula, O(n), for
+                  signals too large for the cascade to be run in a test.
 """
 
 import numpy as np
@@ -222,6 +224,28 @@ def closed_form(m, exact=False):
     if exact:
         return out
     return out.astype(np.float64) * (2.0 ** (-m / 2.0))
+
+
+def coefficient(x, i, exact=None, chunk=1 << 22):
+    """y_i = sum_j H_m[i, j] x_j with the entries of closed_form:
+    2^{-m/2} (-1)^{popcount(bitrev_m(i) & j)} (float, in float64), or the
+    +-1 entries summed exactly in int64 (integer input).  One row of eq. (1)
+    in O(n) time and O(chunk) memory, for single outputs of large signals."""
+    x = np.asarray(x).reshape(-1)
+    n = x.shape[0]
+    m = log2_exact(n)
+    ex = _is_exact(x, exact)
+    r = np.int64(bitrev(int(i), m))
+    acc = 0 if ex else 0.0
+    for lo in range(0, n, chunk):
+        j = np.arange(lo, min(n, lo + chunk), dtype=np.int64)
+        neg = (np.bitwise_count(j & r) & 1).astype(bool)
+        v = x[lo:lo + j.shape[0]]
+        v = v.astype(np.int64) if ex else v.astype(np.float64)
+        acc += v[~neg].sum() - v[neg].sum()
+    if ex:
+        return int(acc)
+    return float(acc) * 2.0 ** (-m / 2.0)
 
 
 def radix2_paley(x, exact=None):

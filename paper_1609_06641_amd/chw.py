@@ -27,6 +27,7 @@ FLAG_PERSISTENT = 1 << 2
 FLAG_MULTI_LAUNCH = 1 << 3
 FLAG_ORDER_SEQUENCY = 1 << 4
 FLAG_ORDER_NATURAL = 1 << 5
+FLAG_THREE_PASS = 1 << 6
 ORDERS = {"dyadic": 0, "sequency": FLAG_ORDER_SEQUENCY, "natural": FLAG_ORDER_NATURAL}
 SIGN_MODES = {"per_element": 0, "shared": 1}
 
@@ -154,11 +155,12 @@ class Plan:
     offsets: None (packed back to back) or batch + 1 int64 element offsets.
     dtype: 'f32', 'bf16', 'f16', 'i32' or 'f64'.  norm: 'ortho' or 'none'.
     order: coefficient order 'dyadic' (Paley, eq. 1), 'sequency' (Walsh) or
-    'natural' (Sylvester).
+    'natural' (Sylvester).  three_pass: signals of 2^20 or more take the three
+    HBM passes that signals above 2^27 always take (FLAG_THREE_PASS).
     """
 
     def __init__(self, log2_sizes, dtype="f32", norm="ortho", offsets=None, graph=False,
-                 persistent=False, flags=0, order="dyadic"):
+                 persistent=False, flags=0, order="dyadic", three_pass=False):
         lib = load()
         import numpy as np
         sizes = np.ascontiguousarray(log2_sizes, dtype=np.int32).ravel()
@@ -173,6 +175,7 @@ class Plan:
                 raise ValueError("offsets needs batch + 1 entries")
         self.offsets = offs_arr
         flags = int(flags) | (FLAG_GRAPH if graph else 0) | (FLAG_PERSISTENT if persistent else 0)
+        flags |= FLAG_THREE_PASS if three_pass else 0
         flags |= ORDERS[order]
         self.order = order
         h = _VP()
@@ -187,6 +190,9 @@ class Plan:
         else:
             self.extent = int(offs_arr[-1])
         self._ws = {}
+        # signals in three passes keep two intermediates in the workspace, so
+        # even an out-of-place forward call needs one
+        self._three = self.describe()["plan"]["three"] > 0
 
     @classmethod
     def haar_walsh(cls, batch, m, dtype="f32", norm="ortho", graph=False):
@@ -205,6 +211,7 @@ class Plan:
                                for i in range(int(batch))] + [np.array([int(batch) << m])])
         self.batch, self.log2_sizes, self.dtype, self.norm = int(sizes.size), sizes, dtype, norm
         self.offsets, self.order, self.extent, self._ws, self._h = offs, "dyadic", int(batch) << m, {}, h
+        self._three = self.describe()["plan"]["three"] > 0
         return self
 
     # -- plan queries ---------------------------------------------------------
@@ -292,7 +299,7 @@ class Plan:
         if workspace is None:
             narrow = self.dtype in ("bf16", "f16")
             rounds = signed[2] if signed else 1
-            need = self.workspace_size() > 0 and (adjoint or narrow or rounds > 1 or
+            need = self.workspace_size() > 0 and (adjoint or narrow or rounds > 1 or self._three or
                                                   out.data_ptr() == x.data_ptr())
             workspace = self._workspace(x.device, need)
         else:

@@ -170,7 +170,8 @@ std::string tuning_key(int dt, int order, uint32_t flags, const std::vector<int3
         if (m >= 0 && m <= 30) ++cnt[m];
     std::string k = "dt" + std::to_string(dt) + "/order" + std::to_string(order) + "/form" +
                     std::to_string((flags & CHW_FLAG_PERSISTENT) ? 2 :
-                                   (flags & CHW_FLAG_MULTI_LAUNCH) ? 1 : 0) + "/m";
+                                   (flags & CHW_FLAG_MULTI_LAUNCH) ? 1 : 0) +
+                    ((flags & CHW_FLAG_THREE_PASS) ? "/three" : "") + "/m";
     for (int m = 0; m <= 30; ++m) {
         if (!cnt[m]) continue;
         int bl = 0;
@@ -386,7 +387,19 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         }
         a.signs = in_launch_rounds ? sg.w : w_round;
         a.rounds = in_launch_rounds ? k : 1;
-        const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, adj);
+        // the middle pass of three-pass signals: first-pass tiles from one
+        // intermediate to the other, in the compute type, no scale, no signs
+        // (adjoint: from the second back to the first)
+        const bool mid = r.role == 1;
+        a.in = mid ? inter : x;
+        a.out = mid ? inter : y;
+        a.inter_is_io = mid ? 0 : inter_is_io;
+        a.ortho = mid ? 0 : (p->norm == CHW_ORTHONORMAL ? 1 : 0);
+        if (mid) {
+            a.signs = nullptr;
+            a.rounds = 1;
+        }
+        const ItemsVariant *v = find_items_variant(mid ? compute_dt(p->dt) : p->dt, r.K, r.LR, adj);
         if (!v || (r.persistent && !v->launch_persistent))
             return fail(CHW_ERR_UNSUPPORTED, "no tile kernel for dtype %d, K=%d, LR=%d", p->dt,
                         r.K, r.LR);
@@ -552,7 +565,7 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
             if (intervals_overlap(ws, wsb, y, bytes))
                 return fail(CHW_ERR_INVALID_ARGUMENT, "workspace overlaps y");
             inter = ws;
-        } else if (!adj && !narrow && x != y) {
+        } else if (!adj && !narrow && x != y && p->built.n_three == 0) {
             inter = y;  // out-of-place forward: the intermediate goes through y
             inter_is_io = 1;
             if (sg.w && sg.rounds > 1)
@@ -652,7 +665,7 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
         return fail(CHW_ERR_UNSUPPORTED, "the integer type has only the unnormalized form");
     const uint32_t known = CHW_FLAG_GRAPH | CHW_FLAG_NO_AUTOTUNE | CHW_FLAG_PERSISTENT |
                            CHW_FLAG_MULTI_LAUNCH | CHW_FLAG_ORDER_SEQUENCY |
-                           CHW_FLAG_ORDER_NATURAL;
+                           CHW_FLAG_ORDER_NATURAL | CHW_FLAG_THREE_PASS;
     if (flags & ~known) return fail(CHW_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", flags & ~known);
     if ((flags & CHW_FLAG_PERSISTENT) && (flags & CHW_FLAG_MULTI_LAUNCH))
         return fail(CHW_ERR_INVALID_ARGUMENT, "PERSISTENT and MULTI_LAUNCH are exclusive");
@@ -660,6 +673,10 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
         return fail(CHW_ERR_INVALID_ARGUMENT, "ORDER_SEQUENCY and ORDER_NATURAL are exclusive");
     if ((flags & (CHW_FLAG_ORDER_SEQUENCY | CHW_FLAG_ORDER_NATURAL)) && (flags & CHW_FLAG_PERSISTENT))
         return fail(CHW_ERR_UNSUPPORTED, "the persistent launch computes the dyadic order only");
+    if ((flags & CHW_FLAG_THREE_PASS) && (flags & CHW_FLAG_PERSISTENT))
+        return fail(CHW_ERR_INVALID_ARGUMENT, "THREE_PASS and PERSISTENT are exclusive");
+    if ((flags & CHW_FLAG_THREE_PASS) && (flags & (CHW_FLAG_ORDER_SEQUENCY | CHW_FLAG_ORDER_NATURAL)))
+        return fail(CHW_ERR_UNSUPPORTED, "three-pass signals compute the dyadic order only");
     const int dt = (int)dtype;
     const int maxm = dtype == CHW_F64 ? CHW_MAX_LOG2_F64 : CHW_MAX_LOG2;
     const int es = elem_bytes(dt);
@@ -721,6 +738,7 @@ chw_status chw_plan(chw_plan_t *plan, int64_t batch, const int32_t *log2_sizes,
     if (p->extent > (((int64_t)1 << 62) / 8)) return bad(fail(CHW_ERR_OUT_OF_MEMORY, "extent overflows"));
     PlanConfig cfg;
     if (flags & CHW_FLAG_PERSISTENT) cfg.exec = 2;
+    if (flags & CHW_FLAG_THREE_PASS) cfg.three_min = 20;
     if (flags & CHW_FLAG_ORDER_SEQUENCY) cfg.order = ORDER_SEQUENCY;
     if (flags & CHW_FLAG_ORDER_NATURAL) cfg.order = ORDER_NATURAL;
     if (!(flags & CHW_FLAG_NO_AUTOTUNE)) {

@@ -63,6 +63,7 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     auto tile_intervals = [&](const std::vector<LaunchRange> &launches, std::vector<Iv> &iv) {
         for (size_t li = 0; li < launches.size(); ++li) {
             const LaunchRange &r = launches[li];
+            if (r.role == 1) continue;  // middle passes work in the workspace (below)
             for (int k = r.begin; k < r.end; ++k) {
                 const Item &it = p.items[k];
                 const int K = r.K;
@@ -160,6 +161,70 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         if (have != need || p.n_multi == 0) {
             *err = "round-boundary tiles do not cover the two-pass signals";
             return false;
+        }
+    }
+    // three-pass signals: the middle pass's first-pass tiles tile the first
+    // intermediate [ws3_first, ws3_first + ws3_elems) exactly once, each
+    // writes inside the second one, and in each direction the middle launches
+    // sit between the launches of the outer passes that touch the
+    // intermediates (forward: after every first-pass tile into W1, before
+    // every last-pass tile from W2)
+    if (p.n_three > 0 || p.ws3_elems > 0) {
+        const int64_t w1 = (int64_t)p.ws3_first, n3 = (int64_t)p.ws3_elems, w2 = w1 + n3;
+        if (w2 + n3 > (int64_t)p.ws_elems) {
+            *err = "three-pass intermediates outside the workspace";
+            return false;
+        }
+        for (int dir = 0; dir < 2; ++dir) {
+            const std::vector<LaunchRange> &L = dir ? p.adj : p.fwd;
+            std::vector<std::pair<int64_t, int64_t>> cover;
+            int mid_lo = 1 << 30, mid_hi = -1;
+            int first_lo = 1 << 30, first_hi = -1, last_lo = 1 << 30, last_hi = -1;
+            for (size_t li = 0; li < L.size(); ++li) {
+                const LaunchRange &r = L[li];
+                for (int k = r.begin; k < r.end; ++k) {
+                    const Item &it = p.items[k];
+                    if (r.role == 1) {
+                        if (!is_first_kind(it.kind) || r.persistent) {
+                            *err = "middle pass with an item that is not a first-pass tile";
+                            return false;
+                        }
+                        const int64_t n = (int64_t)1 << r.K;
+                        const int64_t blk = (int64_t)1 << (it.bits + it.rs);  // the block's size
+                        if (it.io_off < w1 || it.io_off + n > w2 || it.ws_off < w2 ||
+                            it.ws_off + blk > w2 + n3 || it.io_off < it.sig_off ||
+                            it.io_off + n > it.sig_off + blk) {
+                            *err = "middle-pass tile outside its block or the intermediates";
+                            return false;
+                        }
+                        cover.push_back({it.io_off, it.io_off + n});
+                        mid_lo = std::min(mid_lo, (int)li);
+                        mid_hi = std::max(mid_hi, (int)li);
+                    } else if (is_first_kind(it.kind) && it.ws_off >= w1 && it.ws_off < w2) {
+                        first_lo = std::min(first_lo, (int)li);  // outer first pass: W1
+                        first_hi = std::max(first_hi, (int)li);
+                    } else if (it.kind == KIND_LAST && it.ws_off >= w2) {
+                        last_lo = std::min(last_lo, (int)li);    // outer last pass: W2
+                        last_hi = std::max(last_hi, (int)li);
+                    }
+                }
+            }
+            std::sort(cover.begin(), cover.end());
+            int64_t have = 0;
+            for (size_t i = 0; i < cover.size(); ++i) {
+                if (i && cover[i].first < cover[i - 1].second) {
+                    *err = "middle-pass tiles overlap";
+                    return false;
+                }
+                have += cover[i].second - cover[i].first;
+            }
+            const bool order_ok = first_hi >= 0 && last_hi >= 0 &&
+                                  (dir == 0 ? (first_hi < mid_lo && mid_hi < last_lo)
+                                            : (last_hi < mid_lo && mid_hi < first_lo));
+            if (have != n3 || mid_hi < 0 || !order_ok) {
+                *err = "middle pass does not cover the first intermediate between the outer passes";
+                return false;
+            }
         }
     }
     for (int dir = 0; dir < 2; ++dir) {

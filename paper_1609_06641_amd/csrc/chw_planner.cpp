@@ -70,6 +70,36 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
     return found;
 }
 
+int compute_dt(int dt)
+{
+    return dt == DT_BF16 || dt == DT_F16 ? DT_F32 : dt;
+}
+
+bool choose_split3(int m, int dt, Split3 *out)
+{
+    // The first pass over rows of 2^L1 leaves 2^L1 blocks of 2^(m - L1)
+    // elements, each an independent signal (the induction step of the proof
+    // of Theorem 1, applied L1 times); a block larger than a last-pass tile
+    // takes two more passes of its own.  The outer first pass prefers the
+    // widest transposed runs, as the two-pass split does.
+    if (dt == DT_F64) return false;
+    struct Opt { int K1, CC, kind; };
+    const Opt opts[] = {{15, K15_CA, KIND_FIRST_A}, {12, K12_CA, KIND_FIRST_A},
+                        {15, K15_CM, KIND_FIRST_C}, {12, K12_CM, KIND_FIRST_C},
+                        {15, K15_CB, KIND_FIRST_B}, {12, K12_CB, KIND_FIRST_B}};
+    for (const Opt &o : opts) {
+        const int L1 = o.K1 - o.CC, b = m - L1;
+        if (b < o.CC) continue;
+        Split inner;
+        if (!choose_split(b, compute_dt(dt), -1, false, ORDER_DYADIC, false, &inner)) continue;
+        out->m = m;
+        out->outer = Split{m, L1, o.K1, o.CC, o.kind, 0};
+        out->inner = inner;
+        return true;
+    }
+    return false;
+}
+
 namespace {
 
 
@@ -188,6 +218,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     for (int64_t i = 0; i < batch; ++i) {
         const int m = ms[i];
         if (m <= single_max) continue;
+        if (m >= p.cfg.three_min && !persistent) continue;  // three passes, below
         Split sp;
         const bool pipe = p.cfg.pipeline && p.cfg.chunk > 0 && !persistent;
         if (!choose_split(m, dt, p.cfg.split_l1, persistent, p.cfg.order, pipe, &sp))
@@ -253,12 +284,95 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         }
         wsb += (int64_t)1 << m;
     }
-    p.ws_elems = (size_t)wsb;
-    // every configuration runs a subset of the signals above 2^12 in two passes,
-    // so this bounds the workspace of all of them (the size a caller allocates
-    // must not change when the plan is tuned)
+    // ---- three-pass signals ------------------------------------------------
+    // Pass 1: first-pass tiles on x, into the first intermediate W1 (the
+    // signal's blocks of 2^b, b = m - L1, contiguous).  Pass 2 ("middle"):
+    // every block of W1 is a signal of 2^b whose first pass runs from W1 into
+    // the second intermediate W2.  Pass 3: the blocks' last-pass tiles from
+    // W2 into y, block g of the signal landing on y's block g.  Same stages in
+    // the same order as any other split, so the same numbers.
+    struct Three { std::vector<Item> first[2], mid[2], last[2]; } three;
+    int64_t tot3 = 0;
     for (int64_t i = 0; i < batch; ++i)
+        if (ms[i] >= p.cfg.three_min && ms[i] > single_max) {
+            if (persistent)
+                throw std::invalid_argument("the persistent launch takes signals up to 2^21");
+            if (p.cfg.order != ORDER_DYADIC)
+                throw std::invalid_argument("three-pass signals (above 2^27) compute the dyadic "
+                                            "order only");
+            tot3 += (int64_t)1 << ms[i];
+        }
+    const int64_t w1 = wsb, w2 = wsb + tot3;
+    int64_t acc3 = 0;
+    for (int64_t i = 0; i < batch && tot3 > 0; ++i) {
+        const int m = ms[i];
+        if (m < p.cfg.three_min || m <= single_max) continue;
+        Split3 s3;
+        if (!choose_split3(m, dt, &s3))
+            throw std::invalid_argument("no three-pass split covers log2 size " + std::to_string(m));
+        ++p.n_multi;
+        ++p.n_three;
+        bool seen = false;
+        for (const Split3 &q : p.splits3)
+            if (q.m == m) seen = true;
+        if (!seen) p.splits3.push_back(s3);
+        const Split &o = s3.outer, &in = s3.inner;
+        const int L1 = o.L1, b = m - L1, L2 = in.L1, b3 = b - L2;
+        const int64_t a = w1 + acc3, c = w2 + acc3;  // the signal in W1 and W2
+        for (int64_t h0 = 0; h0 < ((int64_t)1 << b); h0 += (int64_t)1 << o.CC) {
+            Item it = blank_item();
+            it.kind = o.kind;
+            it.bits = L1;
+            it.m = m;
+            it.rs = b;
+            it.h0 = (int32_t)h0;
+            it.io_off = off[i] + (h0 << L1);
+            it.ws_off = a;
+            it.sig_off = off[i];
+            three.first[kidx(o.K1)].push_back(it);
+        }
+        const int bpt = 1 << (in.K2 - b3);  // blocks per last-pass tile
+        for (int64_t g = 0; g < ((int64_t)1 << L1); ++g) {
+            const int64_t blk = g << b;      // block g within the signal
+            for (int64_t h0 = 0; h0 < ((int64_t)1 << b3); h0 += (int64_t)1 << in.CC) {
+                Item it = blank_item();
+                it.kind = in.kind;
+                it.bits = L2;
+                it.m = m;
+                it.rs = b3;
+                it.h0 = (int32_t)h0;
+                it.io_off = a + blk + (h0 << L2);  // in the workspace (W1)
+                it.ws_off = c + blk;               // the block's base in W2
+                it.sig_off = a + blk;
+                three.mid[kidx(in.K1)].push_back(it);
+            }
+            for (int64_t tl = 0; tl < ((int64_t)1 << L2) / bpt; ++tl) {
+                Item it = blank_item();
+                it.kind = KIND_LAST;
+                it.bits = b3;
+                it.m = m;  // the orthonormal scale of the whole signal
+                it.count = bpt;
+                it.io_off = off[i] + blk + (tl << in.K2);
+                it.ws_off = c + blk + (tl << in.K2);
+                it.sig_off = off[i] + blk;
+                three.last[kidx(in.K2)].push_back(it);
+            }
+        }
+        acc3 += (int64_t)1 << m;
+    }
+    if (tot3 > 0) turn_ok = false;
+    p.ws3_first = (size_t)w1;
+    p.ws3_elems = (size_t)tot3;
+    wsb += 2 * tot3;
+    p.ws_elems = (size_t)wsb;
+    // every configuration runs a subset of the signals above 2^12 in two passes
+    // (and those of 2^three_min or more in three, with two intermediates), so
+    // this bounds the workspace of all of them (the size a caller allocates
+    // must not change when the plan is tuned)
+    for (int64_t i = 0; i < batch; ++i) {
         if (ms[i] > 12) p.ws_bound += (size_t)1 << ms[i];
+        if (ms[i] >= p.cfg.three_min && ms[i] > 15) p.ws_bound += (size_t)1 << ms[i];
+    }
     if (p.ws_elems > p.ws_bound) throw std::logic_error("workspace bound");
 
     // ---- table and launch order ----------------------------------------------
@@ -324,7 +438,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     // pass of the final chunk.  The adjoint pairs the adjoint first pass of
     // chunk j - 1 with the adjoint last pass of chunk j; its items are copies
     // laid out in that order.  Chunk j's intermediate lives in slot j % 2.
-    if (p.cfg.pipeline && p.cfg.chunk > 0 && !persistent && chunks.size() > 1) {
+    if (p.cfg.pipeline && p.cfg.chunk > 0 && !persistent && chunks.size() > 1 && tot3 == 0) {
         int64_t slot = 0;
         std::vector<int64_t> start(chunks.size(), -1);
         for (size_t j = 0; j < chunks.size(); ++j) {
@@ -382,6 +496,21 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             }
         for (int k = 0; k < 2; ++k)
             if (f[k].end > f[k].begin) p.adj.push_back(f[k]);
+    }
+    if (tot3 > 0) {
+        LaunchRange f[2], md[2], l[2];
+        for (int k = 0; k < 2; ++k) append(three.first[k], k == 0 ? 12 : 15, &f[k]);
+        for (int k = 0; k < 2; ++k) {
+            append(three.mid[k], k == 0 ? 12 : 15, &md[k]);
+            md[k].role = 1;
+        }
+        for (int k = 0; k < 2; ++k) append(three.last[k], k == 0 ? 12 : 15, &l[k]);
+        for (const LaunchRange *g : {f, md, l})
+            for (int k = 0; k < 2; ++k)
+                if (g[k].end > g[k].begin) p.fwd.push_back(g[k]);
+        for (const LaunchRange *g : {l, md, f})
+            for (int k = 0; k < 2; ++k)
+                if (g[k].end > g[k].begin) p.adj.push_back(g[k]);
     }
     if (turn_ok && chunks.size() == 1 && !turn_items.empty()) {
         // one launch per first-pass row count (the adjoint's prefetching form is
@@ -523,7 +652,19 @@ std::string describe_plan(const BuiltPlan &p)
                       i ? ", " : "", q.m, q.L1, q.K1, q.CC, q.K2);
         s += buf;
     }
+    s += "], \"splits3\": [";
+    for (size_t i = 0; i < p.splits3.size(); ++i) {
+        const Split3 &q = p.splits3[i];
+        std::snprintf(buf, sizeof buf,
+                      "%s{\"m\": %d, \"L1\": %d, \"K1\": %d, \"rows_log2\": %d, \"L2\": %d, "
+                      "\"K2\": %d, \"rows2_log2\": %d, \"K3\": %d}",
+                      i ? ", " : "", q.m, q.outer.L1, q.outer.K1, q.outer.CC, q.inner.L1,
+                      q.inner.K1, q.inner.CC, q.inner.K2);
+        s += buf;
+    }
     s += "], ";
+    std::snprintf(buf, sizeof buf, "\"three\": %lld, ", (long long)p.n_three);
+    s += buf;
     // elements a launch takes through its part of the transform: every
     // element of its tiles (a whole-signal item counts its signal once)
     auto elements = [&](const LaunchRange &r) {
@@ -544,8 +685,8 @@ std::string describe_plan(const BuiltPlan &p)
             const LaunchRange &r = v[i];
             std::snprintf(buf, sizeof buf,
                           "%s{\"K\": %d, \"LR\": %d, \"begin\": %d, \"end\": %d, \"persistent\": %d, "
-                          "\"stream\": %d, \"elements\": %lld}",
-                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent, r.stream,
+                          "\"stream\": %d, \"role\": %d, \"elements\": %lld}",
+                          i ? ", " : "", r.K, r.LR, r.begin, r.end, r.persistent, r.stream, r.role,
                           (long long)elements(r));
             s += buf;
         }

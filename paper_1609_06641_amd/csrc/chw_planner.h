@@ -53,6 +53,9 @@ struct PlanConfig {
                         // run the prefetching kernel (a workgroup loops over
                         // items and fetches the next tile while the current
                         // one runs; one such workgroup fills a CU's LDS)
+    int three_min = 28; // signals of 2^three_min elements or more run in three
+                        // HBM passes (set from the plan's flags, not a tuning
+                        // choice: the workspace bound depends on it)
     int occupancy = 0;  // workgroups per CU of the looping launches (the
                         // persistent kernel, the prefetching kernels): their
                         // grid is min(items, occupancy x CUs); 0 = as many as
@@ -71,6 +74,12 @@ struct LaunchRange {
                          // workgroup per item
     int single_pass = 0; // 1: single-pass tiles only (all rounds of a signed
                          // call run inside the launch)
+    int role = 0;        // 0: tiles read / write x, y and the workspace as
+                         // their kind says; 1: the middle pass of three-pass
+                         // signals, whose first-pass tiles read the first
+                         // intermediate (offsets io_off, in the workspace)
+                         // and write the second (adjoint: the other way),
+                         // in the compute type, with no scale and no signs
 };
 
 // Smallest launch of single-pass 2^15-element tiles that runs the prefetching
@@ -91,6 +100,19 @@ struct Split {
     int m, L1, K1, CC, kind, K2;
 };
 
+// Three-pass split: a first pass over rows of 2^L1 (split `outer`, whose
+// blocks of 2^(m - L1) are then too large for one last-pass tile), after which
+// every block is an independent signal of 2^(m - L1) elements taken through
+// the two passes of split `inner`.
+struct Split3 {
+    int m;
+    Split outer, inner;
+};
+
+// Compute type of a dtype's kernels (the type of the intermediates): the
+// middle pass of three-pass signals runs the kernels of this type.
+int compute_dt(int dt);
+
 struct BuiltPlan {
     PlanConfig cfg;
     std::vector<Item> items;
@@ -106,9 +128,15 @@ struct BuiltPlan {
     // first pass is not in 2^15-element tiles)
     std::vector<LaunchRange> turn;
     std::vector<Split> splits;        // distinct splits in use
+    std::vector<Split3> splits3;      // distinct three-pass splits in use
     size_t ws_elems = 0;              // compact intermediate of this configuration
     size_t ws_bound = 0;              // intermediate bound over every configuration
     int64_t n_single = 0, n_multi = 0, n_tiny = 0;
+    int64_t n_three = 0;              // signals in three passes (counted in n_multi too)
+    size_t ws3_first = 0;             // workspace element where the three-pass
+                                      // signals' first intermediates begin
+    size_t ws3_elems = 0;             // their elements (the second
+                                      // intermediates follow at ws3_first + ws3_elems)
 };
 
 // Row counts (log2) of the first-pass variants compiled for each tile size.
@@ -131,6 +159,10 @@ int compute_bytes(int dt);
 // the compiled variants covers m.
 bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool last15,
                   Split *out);
+
+// Choose the three-pass split of a dyadic-order signal of 2^m elements: the
+// widest first-pass runs whose blocks have a two-pass split; false when none.
+bool choose_split3(int m, int dt, Split3 *out);
 
 // Build items and launch ranges.  Throws std::bad_alloc on allocation failure,
 // std::invalid_argument when a signal cannot be planned.

@@ -59,7 +59,9 @@ def _plan_raw(sizes, offsets=None, dtype=0, norm=0, flags=0, batch=None):
     (dict(sizes=[10], flags=(1 << 2) | (1 << 3)), 1),  # exclusive flags
     (dict(sizes=[-1]), 1),
     (dict(sizes=[31]), 1),
-    (dict(sizes=[28]), 2),                             # beyond the largest supported size
+    (dict(sizes=[30]), 0),                             # the largest size (three passes)
+    (dict(sizes=[28], flags=1 << 4), 2),               # three passes: dyadic order only
+    (dict(sizes=[20], flags=(1 << 6) | (1 << 2)), 1),  # THREE_PASS with PERSISTENT
     (dict(sizes=[21], dtype=4), 2),                    # F64 limit
     (dict(sizes=[4, 4], offsets=[0, 8, 24]), 1),       # overlap
     (dict(sizes=[4, 4], offsets=[0, 16, 20]), 1),      # end below last signal
@@ -695,3 +697,47 @@ def test_occupancy_option():
     assert p.describe()["plan"]["config"]["occupancy"] == 2
     with pytest.raises(chw.CHWError):
         p.set_option("occupancy", 33)
+
+
+@pytest.mark.parametrize("sizes,flag", [([28], False), ([29], False), ([30, 20, 12, 3], False),
+                                        ([20, 20, 12], True), ([23, 21, 16, 10, 2], True)])
+def test_three_pass_plan_shape(sizes, flag):
+    # signals above 2^27 (or of 2^20 and more with the THREE_PASS flag) take a
+    # first pass into one intermediate, a middle pass between the two
+    # intermediates and a last pass into y; the forward runs them in that
+    # order and the adjoint in reverse, the workspace holds both intermediates
+    p = chw.Plan(sizes, three_pass=flag)
+    p.check()
+    d = p.describe()["plan"]
+    lim = 20 if flag else 28
+    three = [m for m in sizes if m >= lim]
+    assert d["three"] == len(three)
+    assert sorted(q["m"] for q in d["splits3"]) == sorted(set(three))
+    for q in d["splits3"]:
+        assert q["L1"] + q["L2"] < q["m"] and q["m"] - q["L1"] - q["L2"] <= q["K3"]
+    roles = [r["role"] for r in d["forward"]]
+    assert roles.count(1) >= 1 and [r["role"] for r in d["backward"]].count(1) == roles.count(1)
+    mid = [i for i, r in enumerate(d["forward"]) if r["role"] == 1]
+    # elements through the middle pass: the three-pass signals once
+    assert sum(d["forward"][i]["elements"] for i in mid) == sum(1 << m for m in three)
+    two = sum(1 << m for m in sizes if 12 < m < lim)
+    assert p.workspace_size() == 4 * (two + 2 * sum(1 << m for m in three))
+    # options do not change the workspace bound
+    for k, v in (("lr12", 5), ("lr15", 6), ("stream", 0), ("chunk", 1 << 22)):
+        q = chw.Plan(sizes, three_pass=flag)
+        q.set_option(k, v)
+        q.check()
+        assert q.workspace_size() == p.workspace_size()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_three_pass_random_plans(seed):
+    rng = np.random.default_rng(4400 + seed)
+    sizes = sorted((int(v) for v in rng.integers(0, 25, int(rng.integers(1, 12)))), reverse=True)
+    p = chw.Plan(sizes, dtype=["f32", "bf16", "i32"][seed % 3],
+                 norm="none" if seed % 3 == 2 else "ortho", three_pass=True)
+    for k, v in (("lr12", int(rng.choice([5, 6]))), ("lr15", int(rng.choice([5, 6]))),
+                 ("stream", int(rng.integers(0, 3))), ("single15", int(rng.integers(0, 2)))):
+        p.set_option(k, v)
+    p.check()
+    assert p.describe()["plan"]["three"] == sum(1 for m in sizes if m >= 20)

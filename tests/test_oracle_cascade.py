@@ -264,3 +264,35 @@ def test_metrics():
     r = metrics.rel_l2(yh, y)
     assert np.isclose(r[0], 0.1) and np.isclose(r[1], 0.1)
     assert metrics.exact_equal(np.array([1, -2]), np.array([1, -2], dtype=np.int32))
+
+
+@pytest.mark.parametrize("m", [1, 3, 6, 9])
+def test_coefficient_rows_of_eq1(m):
+    # each output of the O(n) single-coefficient form equals the row of the
+    # dense H_m of eq. (1) applied to the vector (integer: exactly; float:
+    # to rounding), and, for float input, the cascade's output
+    from oracle import dense
+    rng = np.random.default_rng(900 + m)
+    n = 1 << m
+    xi = rng.integers(-128, 128, n)
+    xf = rng.standard_normal(n)
+    Hi = dense.hadamard_paley(m, exact=True)
+    Hf = dense.hadamard_paley(m)
+    yc = cascade.chw_forward(xf)
+    for i in range(n):
+        assert cascade.coefficient(xi, i, chunk=5) == int(Hi[i] @ xi)
+        got = cascade.coefficient(xf, i, chunk=7)
+        assert abs(got - Hf[i] @ xf) <= 1e-12 * (1 + abs(got))
+        assert abs(got - yc[i]) <= 1e-12 * (1 + abs(got))
+
+
+def test_coefficient_catches_a_wrong_row():
+    # a planted mistake (the row index not bit-reversed) changes the result
+    m = 5
+    x = np.random.default_rng(1).standard_normal(1 << m)
+    i = 1  # bitrev_5(1) = 16 != 1
+    good = cascade.coefficient(x, i)
+    r = np.int64(i)
+    j = np.arange(1 << m, dtype=np.int64)
+    wrong = float(np.sum(np.where(np.bitwise_count(j & r) & 1, -x, x))) * 2.0 ** (-m / 2)
+    assert abs(good - wrong) > 1e-6
