@@ -156,13 +156,15 @@ def roofline(bytes_per_elem, launches_ms, launches, profile, total_elems):
     }
 
 
-# Planner options timed by default (the same kernels every run, so that the
-# stored profiles name them): the planner's own choices for the uniform
-# batches; for the ragged form one launch per pass replayed as a graph and a
-# first pass of 2^8 levels (the autotuner's usual pick on this workload).
+# Planner options of the profiling runs (--workload, and --plan-config-free
+# runs of the ragged workload's profile): the planner's own choices for the
+# uniform batches; for the ragged form one launch per pass replayed as a graph,
+# a first pass of 2^8 levels, 2^5 registers in the 2^12-element tiles and
+# prefetching in every eligible launch (what the autotuner picks for the BF16
+# ragged workload, which the default run autotunes).
 BENCH_CONFIG = {"plan": {},
-                "ragged": {"exec": 0, "lr15": 5, "single15": 1, "split_l1": 8,
-                           "stream": 1}}
+                "ragged": {"exec": 0, "lr12": 5, "lr15": 5, "single15": 1, "split_l1": 8,
+                           "stream": 2}}
 
 
 def configure(plan, args, x, y, ws, key="plan"):

@@ -104,7 +104,7 @@ enum {
     CHW_FLAG_ORDER_SEQUENCY = 1u << 4,
     CHW_FLAG_ORDER_NATURAL = 1u << 5,
     /* Run signals of 2^20 elements or more in the three HBM passes that
-       signals above 2^27 always take (see chw_workspace_size): the same
+       signals above 2^25 always take (see chw_workspace_size): the same
        numbers, more traffic.  It exists to check that form at sizes an
        oracle runs in seconds.  Dyadic order only; exclusive with
        CHW_FLAG_PERSISTENT. */
@@ -112,8 +112,8 @@ enum {
 };
 
 /* Largest supported log2 signal size (all dtypes except F64).  Signals above
- * 2^15 elements run in two HBM passes, signals above 2^27 in three (dyadic
- * order only: the other orders stop at 2^27). */
+ * 2^15 elements run in two HBM passes, signals above 2^25 in three (dyadic
+ * order; the other orders take two passes up to 2^27 and stop there). */
 #define CHW_MAX_LOG2 30
 /* Largest supported log2 signal size for CHW_F64. */
 #define CHW_MAX_LOG2_F64 20
@@ -180,7 +180,7 @@ chw_status chw_plan_haar_walsh(chw_plan_t *plan, int64_t batch, int32_t m, chw_d
 
 /* Bytes of device workspace a call may need: the FP32 (FP64 for CHW_F64)
  * intermediate between HBM passes of every signal larger than 2^12 elements,
- * twice over for the signals that take three passes (above 2^27, or 2^20 and
+ * twice over for the signals that take three passes (above 2^25, or 2^20 and
  * above with CHW_FLAG_THREE_PASS), which keep two intermediates.
  * The figure does not depend on tuning or options, so a buffer sized from it
  * stays large enough after chw_autotune / chw_plan_set_option.  Calls whose

@@ -136,6 +136,13 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     const int tiny_max = tiny_max_log2(dt);
     const bool persistent = p.cfg.exec == 2;
     const int single_max = (p.cfg.single15 && !persistent) ? 15 : 12;
+    // signals that take three HBM passes: from 2^three_min in the dyadic
+    // order; the other orders keep two passes up to 2^27 (the only sizes they
+    // support)
+    auto three_pass = [&](int m) {
+        return m >= p.cfg.three_min && m > 15 && !persistent &&
+               (p.cfg.order == ORDER_DYADIC || m > 27);
+    };
 
     // item lists: single-pass BLOCKS per tile size; multi-pass FIRST / LAST
     // per chunk and tile size
@@ -218,7 +225,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     for (int64_t i = 0; i < batch; ++i) {
         const int m = ms[i];
         if (m <= single_max) continue;
-        if (m >= p.cfg.three_min && !persistent) continue;  // three passes, below
+        if (three_pass(m)) continue;  // three passes, below
         Split sp;
         const bool pipe = p.cfg.pipeline && p.cfg.chunk > 0 && !persistent;
         if (!choose_split(m, dt, p.cfg.split_l1, persistent, p.cfg.order, pipe, &sp))
@@ -294,11 +301,9 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     struct Three { std::vector<Item> first[2], mid[2], last[2]; } three;
     int64_t tot3 = 0;
     for (int64_t i = 0; i < batch; ++i)
-        if (ms[i] >= p.cfg.three_min && ms[i] > single_max) {
-            if (persistent)
-                throw std::invalid_argument("the persistent launch takes signals up to 2^21");
+        if (three_pass(ms[i])) {
             if (p.cfg.order != ORDER_DYADIC)
-                throw std::invalid_argument("three-pass signals (above 2^27) compute the dyadic "
+                throw std::invalid_argument("signals above 2^27 (three passes) compute the dyadic "
                                             "order only");
             tot3 += (int64_t)1 << ms[i];
         }
@@ -306,7 +311,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     int64_t acc3 = 0;
     for (int64_t i = 0; i < batch && tot3 > 0; ++i) {
         const int m = ms[i];
-        if (m < p.cfg.three_min || m <= single_max) continue;
+        if (!three_pass(m)) continue;
         Split3 s3;
         if (!choose_split3(m, dt, &s3))
             throw std::invalid_argument("no three-pass split covers log2 size " + std::to_string(m));
@@ -371,7 +376,8 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     // must not change when the plan is tuned)
     for (int64_t i = 0; i < batch; ++i) {
         if (ms[i] > 12) p.ws_bound += (size_t)1 << ms[i];
-        if (ms[i] >= p.cfg.three_min && ms[i] > 15) p.ws_bound += (size_t)1 << ms[i];
+        if (ms[i] >= p.cfg.three_min && ms[i] > 15 && (p.cfg.order == ORDER_DYADIC || ms[i] > 27))
+            p.ws_bound += (size_t)1 << ms[i];
     }
     if (p.ws_elems > p.ws_bound) throw std::logic_error("workspace bound");
 

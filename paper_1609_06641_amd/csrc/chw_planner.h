@@ -53,9 +53,13 @@ struct PlanConfig {
                         // run the prefetching kernel (a workgroup loops over
                         // items and fetches the next tile while the current
                         // one runs; one such workgroup fills a CU's LDS)
-    int three_min = 28; // signals of 2^three_min elements or more run in three
+    int three_min = 26; // signals of 2^three_min elements or more run in three
                         // HBM passes (set from the plan's flags, not a tuning
-                        // choice: the workspace bound depends on it)
+                        // choice: the workspace bound depends on it).  2^26
+                        // and 2^27 could take two, but only with first-pass
+                        // runs of 32 bytes: 2.40 / 2.26 ms per 2^28 elements
+                        // against 1.09 / 1.10 ms in three passes (2^24 and
+                        // 2^25: 0.90 / 0.85 ms in two, 1.10 in three)
     int occupancy = 0;  // workgroups per CU of the looping launches (the
                         // persistent kernel, the prefetching kernels): their
                         // grid is min(items, occupancy x CUs); 0 = as many as

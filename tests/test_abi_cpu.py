@@ -172,7 +172,8 @@ def test_planner_ragged_and_options():
     assert d["single"] == 7        # 3, 6, 6, 6, 12, 13, 15
     assert d["multi"] == 4
     ms = sorted(s["m"] for s in d["splits"])
-    assert ms == [16, 20, 24, 27]
+    assert ms == [16, 20, 24]                        # two passes
+    assert [s["m"] for s in d["splits3"]] == [27]    # three passes above 2^25
     for s in d["splits"]:
         assert s["m"] - s["L1"] <= s["K2"] and s["m"] - s["L1"] >= s["rows_log2"]
     # forced split and register options rebuild the plan
@@ -552,14 +553,21 @@ def test_nodes_validation():
 def test_turn_plan_shape():
     # round-boundary tiles: one 2^15-element tile per 2^15 elements of every
     # two-pass signal, only where the plan qualifies
-    sizes = [16, 20, 21, 24, 26, 12, 3]
+    sizes = [16, 20, 21, 24, 25, 12, 3]
     p = chw.Plan(sizes, dtype="f32")
     p.check()
     turn = p.describe()["plan"]["turn"]
-    # one launch per first-pass row count: 2^7 rows (m = 16, 20, 21), 2^5 (24), 2^3 (26)
-    assert len(turn) == 3 and all(r["K"] == 15 and r["stream"] == 8 for r in turn)
+    # one launch per first-pass row count: 2^7 rows (m = 16, 20, 21), 2^5 (24, 25)
+    assert len(turn) == 2 and all(r["K"] == 15 and r["stream"] == 8 for r in turn)
     assert sum(r["end"] - r["begin"] for r in turn) == sum(1 << (k - 15) for k in sizes if k > 15)
-    assert [r["end"] - r["begin"] for r in turn] == [2 + 32 + 64, 512, 2048]
+    assert [r["end"] - r["begin"] for r in turn] == [2 + 32 + 64, 512 + 1024]
+    # 2^3 rows: a forced first pass of 12 levels
+    b = chw.Plan([20] * 2, dtype="f32")
+    b.set_option("split_l1", 12)
+    b.check()
+    assert [r["end"] - r["begin"] for r in b.describe()["plan"]["turn"]] == [64]
+    # three-pass signals take no round-boundary tiles: the plan has none
+    assert chw.Plan([26, 20], dtype="f32").describe()["plan"]["turn"] == []
     q = chw.Plan(sizes, dtype="f32")
     q.set_option("stream", 0)
     q.check()
@@ -699,17 +707,17 @@ def test_occupancy_option():
         p.set_option("occupancy", 33)
 
 
-@pytest.mark.parametrize("sizes,flag", [([28], False), ([29], False), ([30, 20, 12, 3], False),
+@pytest.mark.parametrize("sizes,flag", [([26], False), ([29], False), ([30, 20, 12, 3], False),
                                         ([20, 20, 12], True), ([23, 21, 16, 10, 2], True)])
 def test_three_pass_plan_shape(sizes, flag):
-    # signals above 2^27 (or of 2^20 and more with the THREE_PASS flag) take a
+    # signals above 2^25 (or of 2^20 and more with the THREE_PASS flag) take a
     # first pass into one intermediate, a middle pass between the two
     # intermediates and a last pass into y; the forward runs them in that
     # order and the adjoint in reverse, the workspace holds both intermediates
     p = chw.Plan(sizes, three_pass=flag)
     p.check()
     d = p.describe()["plan"]
-    lim = 20 if flag else 28
+    lim = 20 if flag else 26
     three = [m for m in sizes if m >= lim]
     assert d["three"] == len(three)
     assert sorted(q["m"] for q in d["splits3"]) == sorted(set(three))
@@ -741,3 +749,15 @@ def test_three_pass_random_plans(seed):
         p.set_option(k, v)
     p.check()
     assert p.describe()["plan"]["three"] == sum(1 for m in sizes if m >= 20)
+
+
+def test_other_orders_keep_two_passes_to_2p27():
+    for order in ("sequency", "natural"):
+        for m in (26, 27):
+            p = chw.Plan([m], order=order)
+            p.check()
+            d = p.describe()["plan"]
+            assert d["three"] == 0 and len(d["splits"]) == 1
+            assert p.workspace_size() == 4 << m
+        with pytest.raises(chw.CHWError):
+            chw.Plan([28], order=order)

@@ -152,7 +152,7 @@ def test_ragged_full_bench_config(dtype):
 
 @pytest.mark.parametrize("m", [23, 25, 26, 27])
 def test_largest_sizes_f32(m):
-    # the largest signals a plan takes (2^27 = CHW_MAX_LOG2), one signal,
+    # large single signals (2^26 and 2^27 take three passes), one signal,
     # out of place and in place, whole signal against the oracle
     torch = gu.torch()
     xh = workloads.float_signals(900 + m, 1, m)

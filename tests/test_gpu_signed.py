@@ -224,14 +224,15 @@ def test_signed_persistent_and_split_forms(dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "i32"])
 @pytest.mark.parametrize("mode", ["shared", "per_element"])
-def test_round_boundary_tiles_bitwise(dtype, mode):
+@pytest.mark.parametrize("sizes,split", [([16, 21, 12, 24, 3, 25, 20], -1), ([20, 12, 3, 21], 12)],
+                         ids=["rows7-5", "rows3"])
+def test_round_boundary_tiles_bitwise(dtype, mode, sizes, split):
     # signed multi-round calls join round r's last pass and round r + 1's
     # first pass (KIND_TURN tiles; the adjoint the other way round): the same
     # bits as one launch pair per round, with and without prefetching, in place
-    # and out of place; every compiled first-pass row count (m = 16, 21: 2^7
-    # rows; 24: 2^5; 26: 2^3)
+    # and out of place; every compiled first-pass row count (m = 16, 20, 21:
+    # 2^7 rows; 24, 25: 2^5; a forced first pass of 12 levels: 2^3)
     t = gu.torch()
-    sizes = [16, 21, 12, 24, 3, 26, 20]
     norm = "none" if dtype == "i32" else "ortho"
     gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
     x = np.concatenate([gen(760 + i, 1, k)[0] for i, k in enumerate(sizes)])
@@ -241,6 +242,8 @@ def test_round_boundary_tiles_bitwise(dtype, mode):
         p = chw.Plan(sizes, dtype=dtype, norm=norm)
         p.set_option("turn", turn)
         p.set_option("stream", stream)
+        if split > 0:
+            p.set_option("split_l1", split)
         plans[(turn, stream)] = p
     ref_plan = plans[(0, 1)]
     assert ref_plan.describe()["plan"]["turn"] == []
