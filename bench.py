@@ -156,15 +156,13 @@ def roofline(bytes_per_elem, launches_ms, launches, profile, total_elems):
     }
 
 
-# Planner options of the profiling runs (--workload, and --plan-config-free
-# runs of the ragged workload's profile): the planner's own choices for the
-# uniform batches; for the ragged form one launch per pass replayed as a graph,
-# a first pass of 2^8 levels, 2^5 registers in the 2^12-element tiles and
-# prefetching in every eligible launch (what the autotuner picks for the BF16
-# ragged workload, which the default run autotunes).
+# Planner options when neither --plan-config nor the tuning file gives them:
+# the planner's own choices for the uniform batches; for the ragged form one
+# launch per pass replayed as a graph with 2^5 registers in the 2^12-element
+# tiles (the tuning file's entry for the ragged workload).
 BENCH_CONFIG = {"plan": {},
-                "ragged": {"exec": 0, "lr12": 5, "lr15": 5, "single15": 1, "split_l1": 8,
-                           "stream": 2}}
+                "ragged": {"exec": 0, "lr12": 5, "lr15": 5, "single15": 1, "split_l1": -1,
+                           "stream": 1}}
 
 
 def configure(plan, args, x, y, ws, key="plan"):
@@ -361,15 +359,16 @@ def bench_forms(args, x, y, m, batch, stream):
     return res
 
 
-def bench_ragged(args, dev, stream, dtype):
-    """The ragged workload (20000 signals, log2 sizes in [6, 20], 2^30
-    elements) in `dtype`: the configuration the autotuner picks among every
-    launch form, replayed as a HIP graph (the reported value), and beside it
-    the one-launch persistent form, autotuned within that form."""
+# Autotuner results for the ragged workloads on gfx950, written by
+# `bench.py --write-tuning` (its header says how); the default run starts its
+# ragged plans from it (the tuning cache), so that every run times the kernels
+# the stored profiles name.  Without the file the run autotunes live.
+TUNING_FILE = os.path.join(ROOT, "paper_1609_06641_amd", "tuning_gfx950.txt")
+
+
+def ragged_inputs(dtype, dev):
     import torch
     import workloads
-    from oracle import c_oracle, metrics
-    from paper_1609_06641_amd import chw
     ks = workloads.ragged_log2_sizes(4001)
     offs = workloads.packed_offsets(ks)
     xr = workloads.ragged_values(4002, ks, offs)
@@ -377,7 +376,47 @@ def bench_ragged(args, dev, stream, dtype):
         xb = torch.from_numpy(xr).to(dev)
     else:
         xb = workloads.to_half_precision(xr, dtype).to(dev)
-    del xr
+    return ks, offs, xb
+
+
+def write_tuning(args, dev, stream):
+    """Autotune the ragged workload's plans (BF16 and FP32; every launch form,
+    and the persistent form) and save the tuning cache to TUNING_FILE."""
+    import torch
+    from paper_1609_06641_amd import chw
+    chw.tuning_clear()
+    for dtype in ("bf16", "f32"):
+        ks, offs, xb = ragged_inputs(dtype, dev)
+        yb = torch.empty_like(xb)
+        for persistent in (False, True):
+            p = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=persistent)
+            ws = torch.empty(max(p.workspace_size(), 16), dtype=torch.uint8, device=dev)
+            p.autotune(xb, yb, workspace=ws, iters=5)
+            log("tuned %s persistent=%d: %s" % (dtype, persistent, p.describe()["plan"]["config"]))
+            p.close()
+            del ws
+        del xb, yb
+        torch.cuda.empty_cache()
+    comment = ("autotuner results for the ragged workload (20000 signals, 2^30 elements; BF16 "
+               "and FP32; all launch forms and the persistent one), 5 timed calls per candidate\n"
+               "written by: python3 bench.py --write-tuning (%s, %s)"
+               % (torch.cuda.get_device_properties(0).gcnArchName, torch.cuda.get_device_name(0)))
+    chw.tuning_save(TUNING_FILE, comment)
+    log("wrote %s (%d entries)" % (TUNING_FILE, chw.tuning_count()))
+
+
+def bench_ragged(args, dev, stream, dtype):
+    """The ragged workload (20000 signals, log2 sizes in [6, 20], 2^30
+    elements) in `dtype`: the configuration the autotuner picks among every
+    launch form, replayed as a HIP graph (the reported value), and beside it
+    the one-launch persistent form, autotuned within that form.  The tuned
+    configurations come from TUNING_FILE when it holds them, else from a live
+    autotuning run."""
+    import torch
+    import workloads
+    from oracle import c_oracle, metrics
+    from paper_1609_06641_amd import chw
+    ks, offs, xb = ragged_inputs(dtype, dev)
     yb = torch.empty_like(xb)
     relems = int(offs[-1])
     es = xb.element_size()
@@ -388,8 +427,8 @@ def bench_ragged(args, dev, stream, dtype):
     def timed(plan, key):
         if args.plan_config:
             configure(plan, args, xb, yb, ws, key=key)
-        else:
-            plan.autotune(xb, yb, workspace=ws, iters=2)
+        elif not plan.describe()["tuned"]:
+            plan.autotune(xb, yb, workspace=ws, iters=2)  # no stored entry: tune now
         fn = lambda: plan.forward(xb, out=yb, workspace=ws)  # noqa: E731
         ms = time_steps(fn, args.steps, args.warmup, stream)
         launches = launch_breakdown(plan, fn, args.steps) if not args.no_launch_timing else [ms]
@@ -397,6 +436,7 @@ def bench_ragged(args, dev, stream, dtype):
         return ms, launches
 
     rp = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True)
+    from_file = bool(rp.describe()["tuned"])
     rms, launches = timed(rp, "ragged")
     torch.cuda.synchronize()
     # parity: a few signals of each size class
@@ -414,6 +454,8 @@ def bench_ragged(args, dev, stream, dtype):
            "ms_per_step": round(rms, 4), "signals": len(ks), "elements": relems,
            "dtype": "%s storage, fp32 compute" % dtype if dtype != "f32" else "f32",
            "plan": d["config"], "autotuned": tuned, "graph": True,
+           "tuning": ("from %s" % os.path.relpath(TUNING_FILE, ROOT)) if from_file and tuned
+                     else ("live" if tuned else "fixed options"),
            "launches_per_call": len(d["forward"]),
            "roofline": roofline(2 * es, launches, plan_launches(rp, dt_code), profile, relems),
            "parity": {"log2_sizes": [int(ks[i]) for i in sel], "max_rel_l2": max(rels)}}
@@ -447,7 +489,9 @@ def run_other(args, dev, stream):
         ks = workloads.ragged_log2_sizes(4001)
         offs = workloads.packed_offsets(ks)
         xv = torch.from_numpy(workloads.ragged_values(w.seed, ks, offs))
-        plan = chw.Plan(ks, dtype=w.dtype, offsets=offs, graph=True, persistent=True)
+        # the configuration of the ragged leg of the default run: the tuning
+        # file's entry when it holds one
+        plan = chw.Plan(ks, dtype=w.dtype, offsets=offs, graph=True)
         elems = int(offs[-1])
     else:
         m = w.log2_sizes[0]
@@ -462,7 +506,8 @@ def run_other(args, dev, stream):
     x = xv.reshape(-1).to(tdt).to(dev)
     y = torch.empty_like(x)
     ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device=dev)
-    configure(plan, args, x, y, ws, key="ragged" if w.name.startswith("ragged") else "plan")
+    if not (plan.describe()["tuned"] and not args.plan_config and not args.tune):
+        configure(plan, args, x, y, ws, key="ragged" if w.name.startswith("ragged") else "plan")
     es = x.element_size()
     k = args.signed_rounds
     if k > 0:
@@ -921,6 +966,8 @@ def main():
     ap.add_argument("--plan-config", help="JSON planner options instead of autotuning")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--write-tuning", action="store_true",
+                    help="autotune the ragged workload's plans and save them to the tuning file")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other configurations of the workload list")
     ap.add_argument("--no-forms", action="store_true",
@@ -955,6 +1002,12 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.write_tuning:
+        write_tuning(args, dev, stream)
+        return
+    if os.path.exists(TUNING_FILE) and not args.plan_config and not args.tune:
+        from paper_1609_06641_amd import chw
+        chw.tuning_load(TUNING_FILE)
     if args.workload in CONFIG_WORKLOADS:
         # one configuration of the workload list, cold and warm (its own line)
         res = bench_diff_config(args, dev, stream) if args.workload == "diff_f32" else \
