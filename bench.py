@@ -190,7 +190,7 @@ def plan_launches(plan, dt_code, direction="forward"):
     out = []
     if d["tiny"]:
         out.append({"name": "chw_tiny_kernel", "elements": d["tiny_elements"], "symbol": None})
-    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST", 5: "FIRST_C", 8: "TURN"}
+    kinds = {1: "BLOCKS", 2: "FIRST_A", 3: "FIRST_B", 4: "LAST", 5: "FIRST_C", 8: "TURN", 9: "FIRST_D"}
     adj = "true" if direction == "backward" else "false"
     for r in d[direction]:
         ca = 7 if r["K"] == 15 else 6

@@ -412,9 +412,12 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
                                      stream, a);
         } else if (r.stream >= 1 && r.stream <= 5) {
             const bool dy = order == ORDER_DYADIC;
-            const void *fn = dy ? v->fn_stream[r.stream - 1] : v->fn_stream_order[order - 1][r.stream - 1];
-            const ItemsLauncher lf = dy ? v->launch_stream[r.stream - 1]
-                                        : v->launch_stream_order[order - 1][r.stream - 1];
+            const int slot = stream_slot(r.stream - 1);
+            const void *fn = slot < 0 ? nullptr
+                             : dy ? v->fn_stream[slot] : v->fn_stream_order[order - 1][slot];
+            const ItemsLauncher lf = slot < 0 ? nullptr
+                                     : dy ? v->launch_stream[slot]
+                                          : v->launch_stream_order[order - 1][slot];
             if (!fn || !lf)
                 return fail(CHW_ERR_UNSUPPORTED, "no prefetching kernel for %d-bit tiles in order %d",
                             r.K, order);
@@ -471,7 +474,7 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int s
             } else {
                 const Item &f = b.items[r.begin];
                 const int cc = 15 - (f.m - f.bits);
-                const int i = cc == K15_CA ? 0 : cc == K15_CM ? 1 : cc == K15_CB ? 2 : -1;
+                const int i = cc == K15_CA ? 0 : cc == K15_CM ? 1 : cc == K15_CB ? 2 : cc == K15_CD ? 3 : -1;
                 if (i >= 0) {
                     sl = v->launch_turn_adj_stream[i];
                     sfn = v->fn_turn_adj_stream[i];
@@ -1211,7 +1214,8 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
     }
     std::vector<int> l1s = {-1};
     if (has_multi)
-        for (int l1 : {15 - K15_CA, 12 - K12_CA, 15 - K15_CM, 12 - K12_CM, 15 - K15_CB, 12 - K12_CB}) {
+        for (int l1 : {15 - K15_CA, 15 - K15_CD, 12 - K12_CA, 15 - K15_CM, 12 - K12_CM, 15 - K15_CB,
+                       12 - K12_CB}) {
             Split sp;
             bool ok = true;
             for (int32_t m : plan->m)

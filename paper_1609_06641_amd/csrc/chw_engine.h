@@ -253,10 +253,14 @@ struct Engine {
     static constexpr int N = L::N, NT = L::NT, R = L::R, J = L::J;
     static constexpr bool NT_IN = CHW_NT_IN, NT_OUT = CHW_NT_OUT, NT_INTER = CHW_NT_INTER;
     static constexpr int CM = mid_rows(K);
+    static constexpr int CD = d_rows(K);
     static_assert(CA >= 2 && CB >= 2 && CA < K && CB < K, "first-pass row counts");
     // row count (log2) of a first-pass kind
     template <int KIND>
-    static constexpr int rows_of() { return KIND == KIND_FIRST_A ? CA : KIND == KIND_FIRST_B ? CB : CM; }
+    static constexpr int rows_of()
+    {
+        return KIND == KIND_FIRST_A ? CA : KIND == KIND_FIRST_B ? CB : KIND == KIND_FIRST_D ? CD : CM;
+    }
 
     // ---- butterflies -------------------------------------------------------
     // One stage on register bit rb: v[i] (bit clear) and v[i | 1 << rb]
@@ -985,6 +989,10 @@ struct Engine {
             if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CM>(it, a));
             else load_transp<CM, BR>(lds, inter, first_base<CM>(it, a), it.h0, it.rs, t);
             break;
+        case KIND_FIRST_D:
+            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CD>(it, a));
+            else load_transp<CD, BR>(lds, inter, first_base<CD>(it, a), it.h0, it.rs, t);
+            break;
         case KIND_LAST:
             if constexpr (!ADJ) load_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t);
             else if constexpr (ORD == ORDER_DYADIC)
@@ -1318,6 +1326,7 @@ struct Engine {
             const int cc = K - (it.m - it.bits);
             if (cc == CA) run_turn_adj_cc<CA>(it, a, lds, t);
             else if (cc == CM) run_turn_adj_cc<CM>(it, a, lds, t);
+            else if (cc == CD) run_turn_adj_cc<CD>(it, a, lds, t);
             else if (cc == CB) run_turn_adj_cc<CB>(it, a, lds, t);
         }
     }
@@ -1329,6 +1338,7 @@ struct Engine {
             const int cc = K - (it.m - it.bits);
             if (cc == CA) finish_turn_cc<CA>(it, a, lds, t);
             else if (cc == CM) finish_turn_cc<CM>(it, a, lds, t);
+            else if (cc == CD) finish_turn_cc<CD>(it, a, lds, t);
             else if (cc == CB) finish_turn_cc<CB>(it, a, lds, t);
         }
     }
@@ -1342,6 +1352,7 @@ struct Engine {
         case KIND_FIRST_A: finish_kind<ADJ, KIND_FIRST_A, ORD>(it, a, lds, t); break;
         case KIND_FIRST_B: finish_kind<ADJ, KIND_FIRST_B, ORD>(it, a, lds, t); break;
         case KIND_FIRST_C: finish_kind<ADJ, KIND_FIRST_C, ORD>(it, a, lds, t); break;
+        case KIND_FIRST_D: finish_kind<ADJ, KIND_FIRST_D, ORD>(it, a, lds, t); break;
         case KIND_LAST: finish_kind<ADJ, KIND_LAST, ORD>(it, a, lds, t); break;
         default: break;
         }

@@ -132,7 +132,7 @@ struct Layout {
         // (K, V, C) -> rotation found with the bank rule above for the
         // compiled row counts (V = 2: the FP64 tiles, 2^12 elements only)
         if constexpr (K >= 15)
-            return V == 4 ? (C == 5 ? 3 : C == 3 ? 1 : 0) : 0;
+            return V == 4 ? (C == 6 ? 4 : C == 5 ? 3 : C == 3 ? 1 : 0) : 0;
         else
             return V == 4 ? (C == 6 ? 4 : C == 4 ? 2 : C == 3 ? 1 : 0) : (C == 4 ? 4 : 0);
     }

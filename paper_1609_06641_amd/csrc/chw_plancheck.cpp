@@ -133,7 +133,8 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
                 }
                 if (it.kind != KIND_TURN || it.bits < 8 ||
                     ((int64_t)it.count << it.bits) != ((int64_t)1 << 15) ||
-                    (cc != K15_CA && cc != K15_CM && cc != K15_CB) || it.rs != it.bits ||
+                    (cc != K15_CA && cc != K15_CM && cc != K15_CB && cc != K15_CD) ||
+                    it.rs != it.bits ||
                     ((it.io_off - it.sig_off) & 32767) != 0 ||
                     (int64_t)it.h0 != ((it.io_off - it.sig_off) >> L1)) {
                     *err = "malformed round-boundary tile";

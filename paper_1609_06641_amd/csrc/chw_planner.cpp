@@ -37,9 +37,10 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
     struct Opt { int K1, CC, kind; };
     // preference: the widest transposed runs first (2^7 rows = 512-byte runs
     // of FP32 in the first pass's store)
-    const Opt opts[] = {{15, K15_CA, KIND_FIRST_A}, {12, K12_CA, KIND_FIRST_A},
-                        {15, K15_CM, KIND_FIRST_C}, {12, K12_CM, KIND_FIRST_C},
-                        {15, K15_CB, KIND_FIRST_B}, {12, K12_CB, KIND_FIRST_B}};
+    const Opt opts[] = {{15, K15_CA, KIND_FIRST_A}, {15, K15_CD, KIND_FIRST_D},
+                        {12, K12_CA, KIND_FIRST_A}, {15, K15_CM, KIND_FIRST_C},
+                        {12, K12_CM, KIND_FIRST_C}, {15, K15_CB, KIND_FIRST_B},
+                        {12, K12_CB, KIND_FIRST_B}};
     const int kmax2 = (dt == DT_F64 || k12_only) ? 12 : 15;
     // the natural order's last pass also stores runs, of 2^(K2 - b) blocks:
     // it takes the larger last-pass tile and the split whose shorter run is
@@ -49,7 +50,8 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
     int best_score = -1;
     for (const Opt &o : opts) {
         if (o.K1 == 15 && (dt == DT_F64 || k12_only)) continue;
-        if (o.kind == KIND_FIRST_C && k12_only) continue;  // whole-signal items: A or B
+        if ((o.kind == KIND_FIRST_C || o.kind == KIND_FIRST_D) && k12_only)
+            continue;  // whole-signal items: A or B
         const int L1 = o.K1 - o.CC;
         if (forced_l1 > 0 && L1 != forced_l1) continue;
         const int b = m - L1;                 // levels left for the second pass
@@ -521,7 +523,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     if (turn_ok && chunks.size() == 1 && !turn_items.empty()) {
         // one launch per first-pass row count (the adjoint's prefetching form is
         // compiled per row count)
-        for (int cc : {K15_CA, K15_CM, K15_CB}) {
+        for (int cc : {K15_CA, K15_CD, K15_CM, K15_CB}) {
             std::vector<Item> v;
             for (const Item &it : turn_items)
                 if (15 - (it.m - it.bits) == cc) v.push_back(it);

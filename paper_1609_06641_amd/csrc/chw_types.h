@@ -35,6 +35,10 @@ enum ItemKind : int32_t {
     // stored transposed into `inter2`.  Fields as KIND_LAST, plus h0 (first
     // row of the tile) and rs (= bits).
     KIND_TURN = 7,
+    // First HBM pass with 2^6 rows in 2^15-element tiles (256-byte FP32
+    // runs): the split of 2^24 signals, whose blocks the 2^7-row tiles would
+    // leave larger than a last-pass tile.
+    KIND_FIRST_D = 8,
 };
 
 // Coefficient order of the transform's output (forward) / input (adjoint).
@@ -46,7 +50,8 @@ enum Order : int { ORDER_DYADIC = 0, ORDER_SEQUENCY = 1, ORDER_NATURAL = 2 };
 
 constexpr bool is_first_kind(int kind)
 {
-    return kind == KIND_FIRST_A || kind == KIND_FIRST_B || kind == KIND_FIRST_C;
+    return kind == KIND_FIRST_A || kind == KIND_FIRST_B || kind == KIND_FIRST_C ||
+           kind == KIND_FIRST_D;
 }
 
 // Middle row count (log2) of the first-pass tiles: 2^5 rows in 2^15-element
@@ -54,6 +59,19 @@ constexpr bool is_first_kind(int kind)
 // splits the wide variant cannot take.
 constexpr int K15_CM = 5, K12_CM = 4;
 constexpr int mid_rows(int K) { return K >= 15 ? K15_CM : K12_CM; }
+// Row count (log2) of the KIND_FIRST_D tiles (2^15-element tiles only; the
+// 2^12-element kernels compile the kind with their middle row count and the
+// planner never gives it to them).
+constexpr int K15_CD = 6;
+constexpr int d_rows(int K) { return K >= 15 ? K15_CD : K12_CM; }
+
+// Slot of a prefetching kernel in a variant's tables, by item kind (BLOCKS,
+// FIRST_A, FIRST_B, LAST, FIRST_C, FIRST_D); -1 for the others.
+constexpr int kNumStreamSlots = 6;
+constexpr int stream_slot(int kind)
+{
+    return kind >= KIND_BLOCKS && kind <= KIND_FIRST_C ? kind : kind == KIND_FIRST_D ? 5 : -1;
+}
 
 // 64-byte work item.  Offsets are element offsets:
 //   io_off : start of the tile's contiguous chunk in x / g / y space

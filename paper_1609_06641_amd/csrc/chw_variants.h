@@ -23,18 +23,18 @@ struct ItemsVariant {
     const void *fn;         // kernel symbol (occupancy queries)
     ItemsLauncher launch_persistent;  // persistent form (K = 12 only), or null
     const void *fn_persistent;
-    ItemsLauncher launch_stream[5];   // prefetching form for items of kind
-    const void *fn_stream[5];         // BLOCKS, FIRST_A, FIRST_B, LAST, FIRST_C
+    ItemsLauncher launch_stream[kNumStreamSlots];  // prefetching form for items
+    const void *fn_stream[kNumStreamSlots];        // of each kind, by stream_slot()
     ItemsLauncher launch_order[2];    // one workgroup per item, sequency and
                                       // natural coefficient order
-    ItemsLauncher launch_stream_order[2][5];  // forward prefetching forms of
-    const void *fn_stream_order[2][5];        // those orders (K = 15), by kind
+    ItemsLauncher launch_stream_order[2][kNumStreamSlots];  // forward prefetching forms of
+    const void *fn_stream_order[2][kNumStreamSlots];        // those orders (K = 15), by slot
     ItemsLauncher launch_turn;        // KIND_TURN items (K = 15), one workgroup
                                       // per item (forward or adjoint boundary)
     ItemsLauncher launch_turn_stream; // prefetching form (forward)
     const void *fn_turn_stream;
-    ItemsLauncher launch_turn_adj_stream[3];  // prefetching adjoint form per
-    const void *fn_turn_adj_stream[3];        // row count: 2^CA, 2^CM, 2^CB
+    ItemsLauncher launch_turn_adj_stream[4];  // prefetching adjoint form per
+    const void *fn_turn_adj_stream[4];        // row count: 2^CA, 2^CM, 2^CB, 2^CD
 };
 
 struct TinyVariant {

@@ -557,10 +557,11 @@ def test_turn_plan_shape():
     p = chw.Plan(sizes, dtype="f32")
     p.check()
     turn = p.describe()["plan"]["turn"]
-    # one launch per first-pass row count: 2^7 rows (m = 16, 20, 21), 2^5 (24, 25)
-    assert len(turn) == 2 and all(r["K"] == 15 and r["stream"] == 8 for r in turn)
+    # one launch per first-pass row count: 2^7 rows (m = 16, 20, 21), 2^6 (24),
+    # 2^5 (25)
+    assert len(turn) == 3 and all(r["K"] == 15 and r["stream"] == 8 for r in turn)
     assert sum(r["end"] - r["begin"] for r in turn) == sum(1 << (k - 15) for k in sizes if k > 15)
-    assert [r["end"] - r["begin"] for r in turn] == [2 + 32 + 64, 512 + 1024]
+    assert [r["end"] - r["begin"] for r in turn] == [2 + 32 + 64, 512, 1024]
     # 2^3 rows: a forced first pass of 12 levels
     b = chw.Plan([20] * 2, dtype="f32")
     b.set_option("split_l1", 12)

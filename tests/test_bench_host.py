@@ -57,6 +57,21 @@ def test_ragged_launch_elements_cover_the_batch():
     assert sum(l["elements"] for l in ls) == one_pass + 2 * two_pass
 
 
+def test_every_configuration_names_its_launches():
+    # each benchmarked workload's plan (and the larger two- and three-pass
+    # sizes) maps every launch to a kernel name and symbol
+    import workloads
+    cases = [w.log2_sizes * w.batch for w in workloads.CONFIGS.values()
+             if len(w.log2_sizes) == 1 and w.dtype != "f64"]
+    assert [24] * 16 in cases
+    cases += [[m] * 2 for m in range(16, 31)]
+    for sizes in cases:
+        p = chw.Plan(sizes, dtype="f32")
+        for direction in ("forward", "backward"):
+            ls = bench.plan_launches(p, 0, direction)
+            assert ls and all(l["name"] for l in ls), sizes
+
+
 def test_profiles_name_their_kernels():
     # the committed summaries carry per-kernel PMC bytes keyed by the symbols
     # plan_launches derives

@@ -141,6 +141,43 @@ def test_backward_default_runs_forward_launches(dtype):
         assert gu.per_signal_rel(gu.host_f64(yb), ref, sizes).max() <= gu.TOL[dtype]
 
 
+@pytest.mark.parametrize("m", [23, 24, 25])
+def test_large_two_pass_sizes(m):
+    # the two-pass sizes above the sweep, each with its own first-pass row count
+    # in 2^15-element tiles (m = 23: 2^7 rows, 24: 2^6, 25: 2^5): forward and
+    # the synthesis kernels, out of place and in place, against the oracle;
+    # int32 bit for bit (inputs in [-8, 7], so |y| < 2^28); and the same bits
+    # as the neighbouring first-pass splits
+    t = gu.torch()
+    xf = workloads.float_signals(900 + m, 1, m).reshape(-1)
+    xi = workloads.int_signals(950 + m, 1, m, lo=-8, hi=7).reshape(-1)
+    ref_f = gu.oracle_packed(xf.astype(np.float64), [m])
+    ref_i = gu.oracle_packed(xi.astype(np.int64), [m])
+    outs = {}
+    for l1 in (-1, 8, 9, 10):
+        if l1 > 0 and not 6 <= m - l1 <= 15:
+            continue
+        pf = chw.Plan([m], dtype="f32")
+        pf.set_option("split_l1", l1)
+        pa = chw.Plan([m], dtype="f32")
+        pa.set_option("split_l1", l1)
+        pa.set_option("adjoint", 1)
+        pi = chw.Plan([m], dtype="i32", norm="none")
+        pi.set_option("split_l1", l1)
+        xd = gu.dev_tensor(xf, "f32")
+        yf = pf.forward(xd)
+        yb = pa.backward(xd)
+        tf = gu.dev_tensor(xf, "f32")
+        pf.forward(tf, out=tf)
+        yi = pi.forward(gu.dev_tensor(xi, "i32"))
+        _sync()
+        assert t.equal(yf, tf) and t.equal(yf, yb), (m, l1)
+        outs[l1] = yf
+        assert gu.per_signal_rel(gu.host_f64(yf), ref_f, [m]).max() <= 1e-5, (m, l1)
+        assert np.array_equal(gu.host_i64(yi), ref_i), (m, l1)
+    assert all(t.equal(o, outs[-1]) for o in outs.values())
+
+
 # ---------------------------------------------------------------------------
 # precision forms: bf16 / f16 storage, FP32 inside every pass
 

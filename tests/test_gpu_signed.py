@@ -231,7 +231,7 @@ def test_round_boundary_tiles_bitwise(dtype, mode, sizes, split):
     # first pass (KIND_TURN tiles; the adjoint the other way round): the same
     # bits as one launch pair per round, with and without prefetching, in place
     # and out of place; every compiled first-pass row count (m = 16, 20, 21:
-    # 2^7 rows; 24, 25: 2^5; a forced first pass of 12 levels: 2^3)
+    # 2^7 rows; 24: 2^6; 25: 2^5; a forced first pass of 12 levels: 2^3)
     t = gu.torch()
     norm = "none" if dtype == "i32" else "ortho"
     gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
