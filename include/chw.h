@@ -99,8 +99,10 @@ enum {
          NATURAL:  Sylvester (Kronecker) order, output k = dyadic coefficient
                    bitrev_m(k).
        Exclusive with each other and with CHW_FLAG_PERSISTENT; plans with an
-       order other than dyadic run one workgroup per tile (no prefetching)
-       and one launch per round of a signed call. */
+       order other than dyadic run their adjoint one workgroup per tile (no
+       prefetching), one launch per round of a signed call, and need the
+       workspace in out-of-place forward calls too (their last pass stores
+       outside the blocks it loads). */
     CHW_FLAG_ORDER_SEQUENCY = 1u << 4,
     CHW_FLAG_ORDER_NATURAL = 1u << 5,
     /* Run signals of 2^20 elements or more in the three HBM passes that
@@ -184,9 +186,10 @@ chw_status chw_plan_haar_walsh(chw_plan_t *plan, int64_t batch, int32_t m, chw_d
  * above with CHW_FLAG_THREE_PASS), which keep two intermediates.
  * The figure does not depend on tuning or options, so a buffer sized from it
  * stays large enough after chw_autotune / chw_plan_set_option.  Calls whose
- * signals all run in one pass, and out-of-place forward F32/I32/F64 calls
- * without three-pass signals (which route the intermediate through y), accept
- * NULL.  A workspace must not be shared by concurrent calls. */
+ * signals all run in one pass, and out-of-place forward F32/I32/F64 calls of
+ * dyadic-order plans without three-pass signals (which route the intermediate
+ * through y), accept NULL.  A workspace must not be shared by concurrent
+ * calls. */
 chw_status chw_workspace_size(chw_plan_t plan, size_t *bytes);
 
 /*

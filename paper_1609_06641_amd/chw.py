@@ -190,9 +190,10 @@ class Plan:
         else:
             self.extent = int(offs_arr[-1])
         self._ws = {}
-        # signals in three passes keep two intermediates in the workspace, so
+        # signals in three passes keep two intermediates in the workspace, and
+        # the other orders' last passes store outside the blocks they load, so
         # even an out-of-place forward call needs one
-        self._three = self.describe()["plan"]["three"] > 0
+        self._ws_always = self.describe()["plan"]["three"] > 0 or order != "dyadic"
 
     @classmethod
     def haar_walsh(cls, batch, m, dtype="f32", norm="ortho", graph=False):
@@ -211,7 +212,7 @@ class Plan:
                                for i in range(int(batch))] + [np.array([int(batch) << m])])
         self.batch, self.log2_sizes, self.dtype, self.norm = int(sizes.size), sizes, dtype, norm
         self.offsets, self.order, self.extent, self._ws, self._h = offs, "dyadic", int(batch) << m, {}, h
-        self._three = self.describe()["plan"]["three"] > 0
+        self._ws_always = self.describe()["plan"]["three"] > 0
         return self
 
     # -- plan queries ---------------------------------------------------------
@@ -299,7 +300,7 @@ class Plan:
         if workspace is None:
             narrow = self.dtype in ("bf16", "f16")
             rounds = signed[2] if signed else 1
-            need = self.workspace_size() > 0 and (adjoint or narrow or rounds > 1 or self._three or
+            need = self.workspace_size() > 0 and (adjoint or narrow or rounds > 1 or self._ws_always or
                                                   out.data_ptr() == x.data_ptr())
             workspace = self._workspace(x.device, need)
         else:

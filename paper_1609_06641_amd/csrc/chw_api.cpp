@@ -568,8 +568,14 @@ chw_status run(chw_plan_t p, int adj, const void *x, void *y, void *ws, void *st
             if (intervals_overlap(ws, wsb, y, bytes))
                 return fail(CHW_ERR_INVALID_ARGUMENT, "workspace overlaps y");
             inter = ws;
-        } else if (!adj && !narrow && x != y && p->built.n_three == 0) {
-            inter = y;  // out-of-place forward: the intermediate goes through y
+        } else if (!adj && !narrow && x != y && p->built.n_three == 0 &&
+                   p->built.cfg.order == ORDER_DYADIC) {
+            // out-of-place forward: the intermediate goes through y.  Only in
+            // the dyadic order, whose last-pass tiles store into the blocks
+            // they loaded; the other orders' last passes store into other
+            // blocks (sequency: block g to block invgray(g); natural: runs
+            // across the signal) that tiles not yet run still have to load.
+            inter = y;
             inter_is_io = 1;
             if (sg.w && sg.rounds > 1)
                 return fail(CHW_ERR_INVALID_ARGUMENT,

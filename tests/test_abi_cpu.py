@@ -440,6 +440,26 @@ def test_signed_argument_validation():
     assert st == 1 and "workspace" in lib.chw_last_error().decode()
 
 
+def test_out_of_place_intermediate_through_y_dyadic_only():
+    # an out-of-place forward call without a workspace routes the two-pass
+    # intermediate through y only in the dyadic order: there every last-pass
+    # tile stores into the blocks it loaded, while the sequency order's tile
+    # for block g stores into block invgray(g) and the natural order's into
+    # runs across the signal, blocks other tiles have yet to load.  Checked
+    # before any device access.
+    lib = chw.load()
+    big = (ctypes.c_char * ((16 << 20) + 64))()
+    b = _aligned(big)
+    xb, yb = ctypes.c_void_p(b), ctypes.c_void_p(b + (8 << 20))
+    for order in ("sequency", "natural"):
+        p = chw.Plan([20, 20], dtype="f32", order=order)
+        assert lib.chw_forward(p.handle, xb, yb, None, None) == 1, order
+        assert "workspace" in lib.chw_last_error().decode()
+    p = chw.Plan([20, 20], dtype="f32")
+    st = lib.chw_forward(p.handle, xb, yb, None, None)
+    assert st != 1 and "workspace" not in lib.chw_last_error().decode()
+
+
 # ---- coefficient orders: host-side plan shape --------------------------------
 
 def test_order_flags_and_plan_shape():

@@ -20,10 +20,12 @@ def _sync():
 def _perm(order, m):
     """Dyadic index of every output position of a signal of 2^m."""
     n = 1 << m
-    if order == "natural":
-        return np.array([int(format(k, "0%db" % m)[::-1], 2) if m else 0 for k in range(n)],
-                        dtype=np.int64)
     k = np.arange(n, dtype=np.int64)
+    if order == "natural":
+        r = np.zeros(n, dtype=np.int64)
+        for b in range(m):
+            r |= ((k >> b) & 1) << (m - 1 - b)
+        return r
     return k ^ (k >> 1)
 
 
@@ -107,11 +109,11 @@ def test_order_signed_rounds(order):
 def test_order_prefetching_bitwise(dtype, order):
     # the forward prefetching kernels of the other orders (full 2^15-element
     # tiles: single-pass 2^13 and 2^15 signals, first and last passes of
-    # 2^17 and 2^22 signals) against one workgroup per tile, bit for bit
+    # 2^17, 2^22 and 2^24 signals) against one workgroup per tile, bit for bit
     t = gu.torch()
     norm = "none" if dtype == "i32" else "ortho"
     gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
-    for sizes in ([13] * 8, [15] * 2, [17] * 3, [22] * 2):
+    for sizes in ([13] * 8, [15] * 2, [17] * 3, [22] * 2, [24]):
         x = np.concatenate([gen(830 + i, 1, k).reshape(-1) for i, k in enumerate(sizes)])
         xd = gu.dev_tensor(x, dtype)
         outs = []
@@ -126,3 +128,28 @@ def test_order_prefetching_bitwise(dtype, order):
             outs.append(p.forward(xd, workspace=ws))
         _sync()
         assert t.equal(outs[0], outs[1]), (order, sizes)
+
+
+@pytest.mark.parametrize("order", ["sequency", "natural"])
+def test_order_out_of_place_without_workspace(order):
+    # an out-of-place forward call of these orders always takes a workspace
+    # (their last-pass tiles store into blocks that other tiles have yet to
+    # load, so y cannot hold the intermediate); the binding supplies one.
+    # Large two-pass signals, one workgroup per tile and prefetching: the
+    # dyadic result permuted, bit for bit.
+    t = gu.torch()
+    sizes = [24, 25]
+    x = np.concatenate([workloads.float_signals(840 + i, 1, k).reshape(-1)
+                        for i, k in enumerate(sizes)])
+    xd = gu.dev_tensor(x, "f32")
+    yd = gu.host_f64(chw.Plan(sizes, dtype="f32").forward(xd))
+    for stream in (0, 1):
+        p = chw.Plan(sizes, dtype="f32", order=order)
+        p.set_option("stream", stream)
+        yo = gu.host_f64(p.forward(xd))
+        _sync()
+        o = 0
+        for k in sizes:
+            n = 1 << k
+            assert np.array_equal(yo[o:o + n], yd[o:o + n][_perm(order, k)]), (order, k, stream)
+            o += n
