@@ -824,14 +824,28 @@ struct Engine {
     // one in the row) takes the sum.  The global layout is the one of
     // store_transp; only which thread writes which vector differs.  Used for
     // 2^15-element tiles of 2^7 rows (L1 = 8) with 2^5 registers, where it
-    // leaves one register round (stages 0 .. 4) instead of two.
+    // leaves one register round (stages 0 .. 4) instead of two, and of 2^6
+    // rows (L1 = 9), where the loaded vectors also run the row's first stages
+    // (first_pre) and one register round is left as well (stages 2 .. 5 for
+    // FP32 input).
     template <int CC, bool BR>
     static constexpr bool merge_ok()
     {
-        return BR && K == 15 && LR == 5 && CC == 7 && sizeof(C) == 4;
+        return BR && K == 15 && LR == 5 && (CC == 7 || CC == 6) && sizeof(C) == 4;
     }
     template <int CC>
     static constexpr int merge_stages() { return LR - pre_bits<C>(); }
+    // stages 0 .. first_pre - 1 of a forward first-pass tile run on its loaded
+    // 16-byte vectors (storage type S) before they reach LDS: where the merged
+    // store leaves more stages than one register round holds
+    template <int CC, bool BR>
+    static constexpr int first_pre()
+    {
+        if constexpr (merge_ok<CC, BR>())
+            return K - CC - merge_stages<CC>() > LR ? pre_bits<S>() : 0;
+        else
+            return 0;
+    }
 
     template <int CC>
     static __device__ __forceinline__ void store_transp_merged(const C *lds, C *dst,
@@ -978,19 +992,27 @@ struct Engine {
             break;
         }
         case KIND_FIRST_A:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CA>(it, a));
+            if constexpr (!ADJ)
+                load_contig<NT_IN, S, first_pre<CA, BR>()>(lds, in, it.io_off, K, 1, nullptr, t,
+                                                          first_signs<CA>(it, a), K);
             else load_transp<CA, BR>(lds, inter, first_base<CA>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_B:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CB>(it, a));
+            if constexpr (!ADJ)
+                load_contig<NT_IN, S, first_pre<CB, BR>()>(lds, in, it.io_off, K, 1, nullptr, t,
+                                                          first_signs<CB>(it, a), K);
             else load_transp<CB, BR>(lds, inter, first_base<CB>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_C:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CM>(it, a));
+            if constexpr (!ADJ)
+                load_contig<NT_IN, S, first_pre<CM, BR>()>(lds, in, it.io_off, K, 1, nullptr, t,
+                                                          first_signs<CM>(it, a), K);
             else load_transp<CM, BR>(lds, inter, first_base<CM>(it, a), it.h0, it.rs, t);
             break;
         case KIND_FIRST_D:
-            if constexpr (!ADJ) load_contig<NT_IN, S>(lds, in, it.io_off, K, 1, nullptr, t, first_signs<CD>(it, a));
+            if constexpr (!ADJ)
+                load_contig<NT_IN, S, first_pre<CD, BR>()>(lds, in, it.io_off, K, 1, nullptr, t,
+                                                          first_signs<CD>(it, a), K);
             else load_transp<CD, BR>(lds, inter, first_base<CD>(it, a), it.h0, it.rs, t);
             break;
         case KIND_LAST:
@@ -1121,7 +1143,10 @@ struct Engine {
         } else if constexpr (is_first_kind(KIND)) {
             constexpr int CC = rows_of<KIND>();
             if constexpr (!ADJ && merge_ok<CC, BR>()) {
-                rounds_ct<false, K - CC - merge_stages<CC>()>(lds, t);
+                constexpr int P = first_pre<CC, BR>();
+                static_assert(L::rounds_from(P) >= 1 && K - CC - merge_stages<CC>() - P <= LR,
+                              "one register round between the loaded vectors and the store");
+                rounds_ct<false, K - CC - merge_stages<CC>(), 0, P>(lds, t);
                 store_transp_merged<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
                 return;
             }
@@ -1220,8 +1245,10 @@ struct Engine {
         const int64_t base = a.inter2_is_io ? it.sig_off
                                             : it.ws_off - ((int64_t)it.h0 << (K - CC));
         if constexpr (merge_ok<CC, true>()) {
-            // round r + 1's stages LR .. L1 - 1 are exactly the merged ones
-            static_assert(K - CC - merge_stages<CC>() == LR, "stages 0 .. LR - 1 ran in turn_round0");
+            // round r + 1's stages LR .. L1 - 1: a register round for those
+            // below the merged ones (2^6 rows: stage 5), then the merged store
+            if constexpr (K - CC - merge_stages<CC>() > LR)
+                rounds_ct<false, K - CC - merge_stages<CC>(), 1>(lds, t);
             store_transp_merged<CC>(lds, static_cast<C *>(a.inter2), base, it.h0, it.rs, t);
         } else {
             rounds_ct<false, K - CC, 1>(lds, t);
@@ -1308,10 +1335,9 @@ struct Engine {
                                                            C *lds, int t)
     {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
-        if constexpr (merge_ok<CC, true>())  // stages L1 - 1 .. LR ran on the gathered vectors
-            static_assert(gather_nst<CC, true>() == LR, "the gather leaves stages LR - 1 .. 0");
-        else
-            rounds_down_to1<J - 1>(lds, K - CC, t);  // round r: stages L1 - 1 .. LR
+        // round r: stages L1 - 1 .. LR, those the gather left (none for 2^7
+        // rows, whose merged stages are exactly these)
+        if constexpr (gather_nst<CC, true>() > LR) rounds_down_to1<J - 1>(lds, gather_nst<CC, true>(), t);
         turn_round_adj(it, a, lds, t);
         rounds<true>(lds, it.bits - LR, t);      // round r - 1: stages bits - LR - 1 .. 0
         store_contig<NT_INTER, C>(lds, static_cast<C *>(a.inter2),
@@ -1468,7 +1494,7 @@ struct Engine {
         }
     }
 
-    template <bool ADJ, int KIND>
+    template <bool ADJ, int KIND, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void stream_put(const Item &it, const LaunchArgs &a,
                                                       const u32x4 *raw, const uint32_t *sw,
                                                       C *lds, int t)
@@ -1488,6 +1514,10 @@ struct Engine {
                     }
                 }
                 if constexpr (KIND == KIND_TURN) pre_stages<V, turn_pre()>(vals, it.bits - LR);
+                if constexpr (is_first_kind(KIND)) {
+                    constexpr int P = first_pre<rows_of<KIND>(), ORD != ORDER_NATURAL>();
+                    if constexpr (P > 0) pre_stages_n<V, P>(vals);
+                }
 #pragma unroll
                 for (int u = 0; u < V; ++u) lb[L::pad(V * NT * k) + u] = vals[u];
             }

@@ -122,31 +122,36 @@ struct Layout {
     // tile element e = (hl << L1) | lo; output o (within the tile) = (rho << C)
     // | hl where rho = bitrev_L1(lo) indexes the output run of 2^C elements.
     // Output vector q = o / V is handled by thread t, iteration k with
-    // q = transp_q(t + NT * k): lanes 0-2 keep eight consecutive vectors (a
-    // 128-byte line for FP32 runs of 32 rows), and the bits above are rotated
-    // by transp_rot so that one wave access spreads over the LDS banks.  A bit
-    // permutation keeps q(t | NT k) = q(t) | q(NT k). ---
+    // q = transp_q(t + NT * k): the low transp_keep lane bits keep consecutive
+    // vectors (eight: a 128-byte line, one run of 32 FP32 rows; sixteen for
+    // runs of 64 FP32 rows, so that a wave stores four whole 256-byte runs),
+    // and the bits above are rotated by transp_rot so that one wave access
+    // spreads over the LDS banks.  A bit permutation keeps q(t | NT k) = q(t)
+    // | q(NT k). ---
+    template <int V, int C>
+    static CHW_HD constexpr int transp_keep() { return V == 4 && C == 6 ? 4 : 3; }
     template <int V, int C>
     static CHW_HD constexpr int transp_rot()
     {
         // (K, V, C) -> rotation found with the bank rule above for the
         // compiled row counts (V = 2: the FP64 tiles, 2^12 elements only)
         if constexpr (K >= 15)
-            return V == 4 ? (C == 6 ? 4 : C == 5 ? 3 : C == 3 ? 1 : 0) : 0;
+            return V == 4 ? (C == 6 ? 3 : C == 5 ? 3 : C == 3 ? 1 : 0) : 0;
         else
-            return V == 4 ? (C == 6 ? 4 : C == 4 ? 2 : C == 3 ? 1 : 0) : (C == 4 ? 4 : 0);
+            return V == 4 ? (C == 6 ? 3 : C == 4 ? 2 : C == 3 ? 1 : 0) : (C == 4 ? 4 : 0);
     }
     template <int V, int C>
     static CHW_HD constexpr int transp_q(int n)
     {
         constexpr int lv = V == 8 ? 3 : V == 4 ? 2 : V == 2 ? 1 : 0;
-        constexpr int W = K - lv - 3, r = transp_rot<V, C>();
+        constexpr int kb = transp_keep<V, C>();
+        constexpr int W = K - lv - kb, r = transp_rot<V, C>();
         if constexpr (W <= 0 || r == 0 || r >= W) {
             return n;
         } else {
-            const int f = (n >> 3) & ((1 << W) - 1);
+            const int f = (n >> kb) & ((1 << W) - 1);
             const int g = ((f << r) | (f >> (W - r))) & ((1 << W) - 1);
-            return (n & 7) | (g << 3);
+            return (n & ((1 << kb) - 1)) | (g << kb);
         }
     }
     // BR = false: the natural-order variant, run rho holds row element rho

@@ -241,10 +241,10 @@ std::string check_variant()
     tr_phase(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
 
     // ---- merged transposed store of 2^15-element tiles with 2^5 registers and
-    // 2^7 rows (4-byte elements): same global layout as the plain store, and
-    // a thread's vector k covers run index bits 0 .. log2(R / V) - 1 = k
-    if constexpr (K == 15 && LR == 5) {
-        constexpr int V = 4, CC = 7, NV = N / (V * NT), L1 = K - CC;
+    // 2^7 or 2^6 rows (4-byte elements): same global layout as the plain
+    // store, and a thread's vector k covers run index bits 0 .. log2(R / V) - 1
+    auto merged_phase = [&](auto ctag) {
+        constexpr int V = 4, CC = decltype(ctag)::value, NV = N / (V * NT), L1 = K - CC;
         Stats ms;
         std::vector<int> seen(N, 0);
         const int rsv = 13;
@@ -287,6 +287,10 @@ std::string check_variant()
                       K, LR, V, CC, ms.ok ? "true" : "false", ms.worst64, ms.worst32);
         out += buf;
         if (!ms.ok) out += ", {\"error\": \"" + ms.err + "\"}";
+    };
+    if constexpr (K == 15 && LR == 5) {
+        merged_phase(std::integral_constant<int, 7>{});
+        merged_phase(std::integral_constant<int, 6>{});
     }
     return out;
 }

@@ -90,6 +90,30 @@ def test_ragged_two_pass_rne(dtype, options):
         assert gu.narrowing_mismatches(gh, gf, dtype) == 0
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_large_two_pass_rne(dtype):
+    # each first-pass row count of the 2^15-element tiles at its largest size
+    # (2^23: 2^7 rows, 2^24: 2^6, 2^25: 2^5), in the dyadic and sequency
+    # orders and with and without prefetching
+    torch = gu.torch()
+    sizes = [24, 23, 25]
+    x32 = np.concatenate([workloads.outlier_signals(9200 + i, 1, k).reshape(-1)
+                          for i, k in enumerate(sizes)])
+    xd = workloads.to_half_precision(x32, dtype).cuda()
+    for order in ("dyadic", "sequency"):
+        for stream in (1, 0):
+            p_h = chw.Plan(sizes, dtype=dtype, order=order)
+            p_f = chw.Plan(sizes, dtype="f32", order=order)
+            for p in (p_h, p_f):
+                p.set_option("stream", stream)
+            yh = p_h.forward(xd)
+            torch.cuda.synchronize()
+            yf = p_f.forward(xd.float())
+            torch.cuda.synchronize()
+            assert gu.narrowing_mismatches(yh, yf, dtype) == 0, (order, stream)
+            del yh, yf
+
+
 def test_ragged_bf16_bench_form_rne():
     # the ragged workload at its full size (20000 signals, 2^30 elements) in
     # the launch configuration the benchmark times, against the FP32 plan of

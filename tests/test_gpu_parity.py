@@ -176,6 +176,12 @@ def test_large_two_pass_sizes(m):
         assert gu.per_signal_rel(gu.host_f64(yf), ref_f, [m]).max() <= 1e-5, (m, l1)
         assert np.array_equal(gu.host_i64(yi), ref_i), (m, l1)
     assert all(t.equal(o, outs[-1]) for o in outs.values())
+    # the sequency order: the same values, rows listed by sign changes
+    ps = chw.Plan([m], dtype="f32", order="sequency")
+    ys = ps.forward(gu.dev_tensor(xf, "f32"))
+    _sync()
+    k = np.arange(1 << m, dtype=np.int64)
+    assert np.array_equal(gu.host_f64(ys), gu.host_f64(outs[-1])[k ^ (k >> 1)])
 
 
 # ---------------------------------------------------------------------------
