@@ -385,8 +385,7 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *               full and of one kind runs as a loop over its items, fetching
  *               the next tile's vectors while the current tile runs;
  *               1 (default): the same, except that a launch of single-pass
- *               tiles prefetches only when every tile is one 2^15-element
- *               signal and there are at least 1024 of them;
+ *               tiles prefetches only when it has at least 1024 of them;
  *               0: one workgroup per tile.  (The adjoint of the sequency and
  *               natural orders always runs one workgroup per tile.)
  *   "turn"      1 (default): signed calls of several rounds join round r's

@@ -242,6 +242,35 @@ __device__ __forceinline__ uint32_t sign_bits(const SignCtx &sc, int64_t g, int6
     return sc.w[b >> 5] >> (uint32_t)(b & 31);
 }
 
+// A per-thread LDS base for accesses at offsets that are compile-time
+// constants once the loops are unrolled.  An LDS instruction carries a 16-bit
+// byte offset, so in a tile larger than 64 KiB (2^15 FP32 elements) every
+// access past 64 KiB from the base would otherwise get an address register of
+// its own, and the optimizer hoists those out of the item loop, where they
+// take registers for the whole kernel.  Offsets of 64 KiB and more go from a
+// second base (the first plus 64 KiB), kept opaque so that it stays one
+// register.  Offsets not known at compile time go from the first base.
+template <typename C, int WORDS>
+struct LdsAt {
+    static constexpr int SPLIT = 65536 / (int)sizeof(C);
+    C *lds;
+    int b0, b1;
+    __device__ __forceinline__ LdsAt(C *l, int b) : lds(l), b0(b), b1(0)
+    {
+        if constexpr (WORDS > SPLIT) {
+            b1 = b + SPLIT;
+            asm("" : "+v"(b1));
+        }
+    }
+    __device__ __forceinline__ C &operator[](int off) const
+    {
+        if constexpr (WORDS > SPLIT) {
+            if (__builtin_constant_p(off) && off >= SPLIT) return lds[b1 + (off - SPLIT)];
+        }
+        return lds[b0 + off];
+    }
+};
+
 // ---------------------------------------------------------------------------
 // the engine
 
@@ -252,6 +281,8 @@ struct Engine {
     using C = typename Types<DT>::C;
     static constexpr int N = L::N, NT = L::NT, R = L::R, J = L::J;
     static constexpr bool NT_IN = CHW_NT_IN, NT_OUT = CHW_NT_OUT, NT_INTER = CHW_NT_INTER;
+    using At = LdsAt<C, L::LDS_WORDS>;
+    using CAt = LdsAt<const C, L::LDS_WORDS>;
     static constexpr int CM = mid_rows(K);
     static constexpr int CD = d_rows(K);
     static_assert(CA >= 2 && CB >= 2 && CA < K && CB < K, "first-pass row counts");
@@ -287,7 +318,7 @@ struct Engine {
     static __device__ __forceinline__ void round_body(C *lds, int t)
     {
         constexpr int lo = L::flo(j, B0), a0 = L::alo(j, B0);
-        C *base = lds + L::pad(L::round_tbase(j, t, B0));
+        const At base(lds, L::pad(L::round_tbase(j, t, B0)));
         C v[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = base[L::pad(L::round_reg(j, i, B0))];
@@ -308,7 +339,7 @@ struct Engine {
     static __device__ __forceinline__ void round_nst(C *lds, int nst, int t)
     {
         constexpr int lo = L::flo(j, B0), a0 = L::alo(j, B0), a1 = L::ahi(j, B0);
-        C *base = lds + L::pad(L::round_tbase(j, t, B0));
+        const At base(lds, L::pad(L::round_tbase(j, t, B0)));
         C v[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = base[L::pad(L::round_reg(j, i, B0))];
@@ -489,7 +520,7 @@ struct Engine {
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         static_assert(NV >= 1, "tile too small for the vector width");
-        C *lb = lds + L::pad(V * t);
+        const At lb(lds, L::pad(V * t));
         const bool full = (list == nullptr) && ((count << bits) >= N);
         const int mask = (1 << bits) - 1;
         C vals[NV][V];
@@ -543,7 +574,7 @@ struct Engine {
                                                         const SignCtx &sg = SignCtx{nullptr, 0, 0})
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
-        const C *lb = lds + L::pad(V * t);
+        const CAt lb(lds, L::pad(V * t));
         const bool full = (list == nullptr) && ((count << bits) >= N);
         const int mask = (1 << bits) - 1;
 #pragma unroll
@@ -591,7 +622,7 @@ struct Engine {
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         if (bits == K) {
-            const C *lb = lds + L::pad((int)rbrev((uint32_t)(V * t), K));
+            const CAt lb(lds, L::pad((int)rbrev((uint32_t)(V * t), K)));
             T *d = dst + (list ? list[0] : off) + V * t;
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
@@ -637,7 +668,7 @@ struct Engine {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         C vals[NV][V];
         if (bits == K) {
-            C *lb = lds + L::pad((int)rbrev((uint32_t)(V * t), K));
+            const At lb(lds, L::pad((int)rbrev((uint32_t)(V * t), K)));
             const T *s = src + (list ? list[0] : off) + V * t;
 #pragma unroll
             for (int k = 0; k < NV; ++k) vload<H>(s + V * NT * k, vals[k]);
@@ -804,7 +835,7 @@ struct Engine {
     {
         constexpr int V = Vec<C>::V, NV = N / (V * NT);
         static_assert(V <= (1 << CC), "a vector must stay inside one run");
-        const C *lb = lds + L::pad(L::template transp_e<V, CC, BR>(t, 0, 0));
+        const CAt lb(lds, L::pad(L::template transp_e<V, CC, BR>(t, 0, 0)));
         C *d = dst + base + h0 + L::template transp_goff<CC>(V * L::template transp_q<V, CC>(t), rs);
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -854,7 +885,7 @@ struct Engine {
     {
         constexpr int V = Vec<C>::V, NV = N / (V * NT), L1 = K - CC, nk = merge_stages<CC>();
         static_assert((1 << nk) == NV && nk < L1, "one vector per value of the merged bits");
-        const C *lb = lds + L::pad(L::template transpm_e<V, CC>(t, 0, 0));
+        const CAt lb(lds, L::pad(L::template transpm_e<V, CC>(t, 0, 0)));
         C vals[NV][V];
 #pragma unroll
         for (int k = 0; k < NV; ++k)
@@ -930,7 +961,7 @@ struct Engine {
                     }
             }
         }
-        C *lb = lds + L::pad(gather_e<CC, BR>(t, 0, 0));
+        const At lb(lds, L::pad(gather_e<CC, BR>(t, 0, 0)));
 #pragma unroll
         for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -1502,7 +1533,7 @@ struct Engine {
         using T = SrcT<ADJ, KIND>;
         constexpr int V = Vec<T>::V, NV = nraw<ADJ, KIND>();
         if constexpr (!ADJ) {
-            C *lb = lds + L::pad(V * t);
+            const At lb(lds, L::pad(V * t));
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
                 C vals[V];
@@ -1530,7 +1561,7 @@ struct Engine {
         } else {
             const int bits = it.bits;
             if (bits == K) {
-                C *lb = lds + L::pad((int)rbrev((uint32_t)(V * t), K));
+                const At lb(lds, L::pad((int)rbrev((uint32_t)(V * t), K)));
 #pragma unroll
                 for (int k = 0; k < NV; ++k) {
                     C vals[V];

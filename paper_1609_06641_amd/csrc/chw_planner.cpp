@@ -537,16 +537,16 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     if (p.cfg.stream) {
         // 2^12-element tiles keep several workgroups per CU, which overlap
         // loads and work by themselves; only 2^15-element tiles prefetch.
-        // In mode 1 single-pass tiles prefetch only when each holds one
-        // signal and the launch has many of them (measured: 8192 x 2^15 gains
-        // 15%; tiles of several 2^13 / 2^14 signals, or launches of a few
-        // hundred tiles, lose to one workgroup per tile); mode 2 prefetches in
+        // In mode 1 single-pass tiles prefetch only when the launch has many
+        // of them (measured for 2^28 elements: 2^15 signals 0.41 against
+        // 0.43 ms, 2^14 0.42 against 0.46, 2^13 0.42 against 0.47, and 1024
+        // tiles of 2^14 signals 55 against 61 us; launches of a few hundred
+        // tiles do better with one workgroup per tile); mode 2 prefetches in
         // every launch that can
         auto form = [&](const LaunchRange &r, bool adj) {
             if (r.K != 15) return 0;
             const int s = stream_source(p.items, r.begin, r.end, r.K, adj);
-            if (s == 1 + KIND_BLOCKS && p.cfg.stream == 1 &&
-                (p.items[r.begin].bits != 15 || r.end - r.begin < kStreamBlocksMin))
+            if (s == 1 + KIND_BLOCKS && p.cfg.stream == 1 && r.end - r.begin < kStreamBlocksMin)
                 return 0;
             return s;
         };

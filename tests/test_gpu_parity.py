@@ -368,12 +368,13 @@ def test_vector_stages_bitwise(dtype):
         assert gu.per_signal_rel(gu.host_f64(res[0][0]), ref, ms, offs).max() <= gu.TOL[dtype]
 
 
-def test_stream_default_single_pass():
-    # the default prefetching rule picks the single-pass kernel for many
-    # one-signal 2^15-element tiles (1024 x 2^15): same bits as one
-    # workgroup per tile, and the oracle's values
-    sizes = [15] * 1024
-    x = workloads.float_signals(910, 1024, 15).reshape(-1)
+@pytest.mark.parametrize("m,batch", [(15, 1024), (14, 2048), (13, 4096)])
+def test_stream_default_single_pass(m, batch):
+    # the default prefetching rule picks the single-pass kernel for launches
+    # of 1024 or more 2^15-element tiles, of one signal or several each: same
+    # bits as one workgroup per tile, and the oracle's values (first signals)
+    sizes = [m] * batch
+    x = workloads.float_signals(910 + m, batch, m).reshape(-1)
     xd = gu.dev_tensor(x, "f32")
     res = []
     for stream in (0, 1):
@@ -385,8 +386,9 @@ def test_stream_default_single_pass():
         res.append((gu.host_f64(p.forward(xd)), gu.host_f64(p.backward(xd, workspace=ws))))
     _sync()
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
-    ref = gu.oracle_packed(gu.host_f64(xd), sizes)
-    assert gu.per_signal_rel(res[1][0], ref, sizes).max() <= 1e-5
+    n = 64 << m
+    ref = gu.oracle_packed(gu.host_f64(xd)[:n], sizes[:64])
+    assert gu.per_signal_rel(res[1][0][:n], ref, sizes[:64]).max() <= 1e-5
 
 
 @pytest.mark.skip(reason="the dependency-counter persistent kernel (exec 1) did not finish "
