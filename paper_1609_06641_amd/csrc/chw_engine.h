@@ -389,18 +389,18 @@ struct Engine {
         }
     }
 
-    // the stages [B0 + j LR, nst) (forward) or [0, nst) (adjoint, B0 = 0)
+    // the stages [B0, nst): increasing (forward) or decreasing (adjoint; the
+    // stages below B0 then run on the stored vectors, see post_bits)
     template <bool ADJ, int j = 0, int B0 = 0>
     static __device__ __forceinline__ void rounds(C *lds, int nst, int t)
     {
-        static_assert(!ADJ || B0 == 0, "the adjoint rounds start at bit 0");
         if constexpr (j < L::rounds_from(B0)) {
             if constexpr (!ADJ) {
                 round<j, false, B0>(lds, nst, t);
                 rounds<false, j + 1, B0>(lds, nst, t);
             } else {
-                round<J - 1 - j, true>(lds, nst, t);
-                rounds<true, j + 1>(lds, nst, t);
+                round<L::rounds_from(B0) - 1 - j, true, B0>(lds, nst, t);
+                rounds<true, j + 1, B0>(lds, nst, t);
             }
         }
     }
@@ -409,9 +409,8 @@ struct Engine {
     template <bool ADJ, int NST, int j = 0, int B0 = 0>
     static __device__ __forceinline__ void rounds_ct(C *lds, int t)
     {
-        static_assert(!ADJ || B0 == 0, "the adjoint rounds start at bit 0");
         if constexpr (j < L::rounds_from(B0)) {
-            constexpr int jj = ADJ ? J - 1 - j : j;
+            constexpr int jj = ADJ ? L::rounds_from(B0) - 1 - j : j;
             constexpr int a0 = L::alo(jj, B0), a1 = L::ahi(jj, B0);
             if constexpr (a0 < NST) {
                 if constexpr (K == 12 && LR == 5) {
@@ -511,6 +510,35 @@ struct Engine {
         }
     }
 
+    // The adjoint's last stages (tile bits POST - 1 .. 0, decreasing) on one
+    // stored vector, below min(POST, lim): the counterpart of pre_stages
+    template <int V, int NB>
+    static __device__ __forceinline__ void post_stages_n(C *v)
+    {
+#pragma unroll
+        for (int b = NB - 1; b >= 0; --b) {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                if (!(i & (1 << b))) {
+                    C x = v[i], y = v[i | (1 << b)];
+                    v[i] = x + y;
+                    v[i | (1 << b)] = x - y;
+                }
+        }
+    }
+    template <int V, int POST>
+    static __device__ __forceinline__ void post_stages(C *v, int lim)
+    {
+        static_assert((1 << POST) <= V && POST <= 3, "post-stages stay inside one vector");
+        if constexpr (POST >= 1) {
+            if (lim >= POST) post_stages_n<V, POST>(v);
+            else if (lim == POST - 1) post_stages_n<V, POST - 1>(v);
+            else if constexpr (POST >= 3) {
+                if (lim == POST - 2) post_stages_n<V, POST - 2>(v);
+            }
+        }
+    }
+
     template <bool H, typename T, int PRE = 0>
     static __device__ __forceinline__ void load_contig(C *lds, const T *src, int64_t off,
                                                        int bits, int count,
@@ -566,12 +594,13 @@ struct Engine {
         }
     }
 
-    template <bool H, typename T>
+    template <bool H, typename T, int POST = 0>
     static __device__ __forceinline__ void store_contig(const C *lds, T *dst, int64_t off,
                                                         int bits, int count,
                                                         const int64_t *list, int t,
                                                         C scale, bool do_scale,
-                                                        const SignCtx &sg = SignCtx{nullptr, 0, 0})
+                                                        const SignCtx &sg = SignCtx{nullptr, 0, 0},
+                                                        int post_lim = 0)
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         const CAt lb(lds, L::pad(V * t));
@@ -584,9 +613,11 @@ struct Engine {
             if (full || blk < count) {
                 C vals[V];
 #pragma unroll
-                for (int u = 0; u < V; ++u) {
-                    vals[u] = lb[L::pad(V * NT * k) + u];
-                    if (do_scale) vals[u] = scale_mul(vals[u], scale);
+                for (int u = 0; u < V; ++u) vals[u] = lb[L::pad(V * NT * k) + u];
+                if constexpr (POST > 0) post_stages<V, POST>(vals, post_lim);
+                if (do_scale) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) vals[u] = scale_mul(vals[u], scale);
                 }
                 const int64_t g = (!full && list) ? list[blk] + (e0 & mask) : off + e0;
                 if (sg.w) {
@@ -1144,6 +1175,13 @@ struct Engine {
         else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, last_scale);
     }
 
+    // Stages below post_bits() of an adjoint tile run on its stored 16-byte
+    // vectors (after the register rounds, before the scale and the diagonal),
+    // so the adjoint's rounds stop at that bit: with 2^5 registers and 4-byte
+    // elements 12 stages take two rounds instead of three, 7 one instead of
+    // two, and no count grows.
+    static constexpr int post_bits() { return LR == 5 && sizeof(C) == 4 ? pre_bits<C>() : 0; }
+
     // stages and store phase of one item of a kind known at compile time
     template <bool ADJ, int KIND, int ORD = ORDER_DYADIC>
     static __device__ __forceinline__ void finish_kind(const Item &it, const LaunchArgs &a,
@@ -1164,13 +1202,15 @@ struct Engine {
                     return;
                 }
             }
-            rounds<ADJ>(lds, it.bits, t);
+            if constexpr (!ADJ) rounds<false>(lds, it.bits, t);
+            else rounds<true, 0, post_bits()>(lds, it.bits, t);
             if constexpr (!ADJ && ORD == ORDER_DYADIC)
                 store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
             else if constexpr (!ADJ)
                 blocks_ordered<ORD, false>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho);
-            else store_contig<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, list, t, sc, ortho,
-                                         SignCtx{a.signs, 0, a.sign_shared});
+            else store_contig<NT_OUT, S, post_bits()>(lds, out, it.io_off, it.bits, it.count, list, t,
+                                                      sc, ortho, SignCtx{a.signs, 0, a.sign_shared},
+                                                      it.bits);
         } else if constexpr (is_first_kind(KIND)) {
             constexpr int CC = rows_of<KIND>();
             if constexpr (!ADJ && merge_ok<CC, BR>()) {
@@ -1181,17 +1221,24 @@ struct Engine {
                 store_transp_merged<CC>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
                 return;
             }
-            rounds_ct<ADJ, ADJ ? gather_nst<CC, BR>() : K - CC>(lds, t);
-            if constexpr (!ADJ) store_transp<CC, BR>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
-            else store_contig<NT_OUT, S>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
-                                         first_signs<CC>(it, a));
+            if constexpr (!ADJ) {
+                rounds_ct<false, K - CC>(lds, t);
+                store_transp<CC, BR>(lds, inter, first_base<CC>(it, a), it.h0, it.rs, t);
+            } else {
+                rounds_ct<true, gather_nst<CC, BR>(), 0, post_bits()>(lds, t);
+                store_contig<NT_OUT, S, post_bits()>(lds, out, it.io_off, K, 1, nullptr, t, sc, ortho,
+                                                     first_signs<CC>(it, a), K);
+            }
         } else {
-            rounds<ADJ>(lds, it.bits, t);
+            if constexpr (!ADJ) rounds<false>(lds, it.bits, t);
+            else rounds<true, 0, post_bits()>(lds, it.bits, t);
             if constexpr (!ADJ && ORD == ORDER_DYADIC)
                 store_paley<NT_OUT, S>(lds, out, it.io_off, it.bits, it.count, nullptr, t, sc, ortho);
             else if constexpr (!ADJ)
                 last_ordered<ORD, false>(lds, out, it, t, sc, ortho);
-            else store_contig<NT_INTER, C>(lds, inter, last_base(it, a), it.bits, it.count, nullptr, t, C(1), false);
+            else store_contig<NT_INTER, C, post_bits()>(lds, inter, last_base(it, a), it.bits, it.count,
+                                                        nullptr, t, C(1), false, SignCtx{nullptr, 0, 0},
+                                                        it.bits);
         }
     }
 
@@ -1370,10 +1417,13 @@ struct Engine {
         // rows, whose merged stages are exactly these)
         if constexpr (gather_nst<CC, true>() > LR) rounds_down_to1<J - 1>(lds, gather_nst<CC, true>(), t);
         turn_round_adj(it, a, lds, t);
-        rounds<true>(lds, it.bits - LR, t);      // round r - 1: stages bits - LR - 1 .. 0
-        store_contig<NT_INTER, C>(lds, static_cast<C *>(a.inter2),
-                                  a.inter2_is_io ? it.io_off : it.ws_off, it.bits, it.count,
-                                  nullptr, t, C(1), false);
+        // round r - 1: stages bits - LR - 1 .. 0, those below post_bits() on
+        // the stored vectors
+        rounds<true, 0, post_bits()>(lds, it.bits - LR, t);
+        store_contig<NT_INTER, C, post_bits()>(lds, static_cast<C *>(a.inter2),
+                                               a.inter2_is_io ? it.io_off : it.ws_off, it.bits,
+                                               it.count, nullptr, t, C(1), false,
+                                               SignCtx{nullptr, 0, 0}, it.bits - LR);
     }
 
     static __device__ __forceinline__ void run_turn_adj(const Item &it, const LaunchArgs &a,
