@@ -1273,15 +1273,18 @@ struct Engine {
     // register bits b are tile bits bits - 1 - b, so the last LR stages of
     // round r (tile bits bits - LR .. bits - 1, in that order) run here too,
     // on register bits LR - 1 .. 0, before the scale and the diagonal.
+    // B > 0: the block size is 2^B, known at compile time (the register
+    // offsets become immediates); B = 0: it.bits at run time.
+    template <int B = 0>
     static __device__ __forceinline__ void turn_round0(const Item &it, const LaunchArgs &a,
                                                        int nst, C *lds, int t)
     {
-        const int bits = it.bits;
+        const int bits = B ? B : it.bits;
         const int o0 = t << LR;  // register round 0: positions o0 .. o0 + R - 1
-        const int rb = L::pad(brev_low(o0, bits));
+        const At rb(lds, L::pad(brev_low(o0, bits)));
         C v[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = lds[rb + L::pad(brev_low(i, bits))];
+        for (int i = 0; i < R; ++i) v[i] = rb[L::pad(brev_low(i, bits))];
         __syncthreads();
 #pragma unroll
         for (int b = LR - 1; b >= 0; --b) bfly(v, b);
@@ -1313,13 +1316,15 @@ struct Engine {
     // stages fit one round from bit 0 already.)
     static constexpr int turn_pre() { return LR == 5 ? pre_bits<C>() : 0; }
 
-    template <int CC>
+    template <int CC, int B>
     static __device__ __forceinline__ void finish_turn_cc(const Item &it, const LaunchArgs &a,
                                                           C *lds, int t)
     {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
-        rounds<false, 0, turn_pre()>(lds, it.bits - LR, t);  // round r's stages below the last LR
-        turn_round0(it, a, K - CC, lds, t);
+        // round r's stages below the last LR
+        if constexpr (B > 0) rounds_ct<false, B - LR, 0, turn_pre()>(lds, t);
+        else rounds<false, 0, turn_pre()>(lds, it.bits - LR, t);
+        turn_round0<B>(it, a, K - CC, lds, t);
         const int64_t base = a.inter2_is_io ? it.sig_off
                                             : it.ws_off - ((int64_t)it.h0 << (K - CC));
         if constexpr (merge_ok<CC, true>()) {
@@ -1359,10 +1364,11 @@ struct Engine {
     // applies D_r, runs round r - 1's first adjoint last-pass stages (tile bits
     // bits - 1 .. bits - LR of the Paley-gathered tile, which are register bits
     // 0 .. LR - 1) and writes the values at their Paley-gathered places.
+    template <int B = 0>
     static __device__ __forceinline__ void turn_round_adj(const Item &it, const LaunchArgs &a,
                                                           C *lds, int t)
     {
-        const int bits = it.bits;
+        const int bits = B ? B : it.bits;
         const int o0 = t << LR;
         const C *nb = lds + L::pad(o0);
         C v[R];
@@ -1384,7 +1390,7 @@ struct Engine {
         }
 #pragma unroll
         for (int b = 0; b < LR; ++b) bfly(v, b);
-        C *wb = lds + L::pad(brev_low(o0, bits));
+        const At wb(lds, L::pad(brev_low(o0, bits)));
 #pragma unroll
         for (int i = 0; i < R; ++i) wb[L::pad(brev_low(i, bits))] = v[i];
         __syncthreads();
@@ -1407,23 +1413,61 @@ struct Engine {
         finish_turn_adj<CC>(it, a, lds, t);
     }
 
-    // the adjoint boundary after its transposed gather
-    template <int CC>
-    static __device__ __forceinline__ void finish_turn_adj(const Item &it, const LaunchArgs &a,
-                                                           C *lds, int t)
+    // the adjoint boundary after its transposed gather (B as in turn_round0)
+    template <int CC, int B>
+    static __device__ __forceinline__ void finish_turn_adj_b(const Item &it, const LaunchArgs &a,
+                                                             C *lds, int t)
     {
         static_assert(L::flo(0) == 0 && L::J >= 2, "register round 0 covers tile bits 0 .. LR - 1");
+        const int bits = B ? B : it.bits;
         // round r: stages L1 - 1 .. LR, those the gather left (none for 2^7
         // rows, whose merged stages are exactly these)
         if constexpr (gather_nst<CC, true>() > LR) rounds_down_to1<J - 1>(lds, gather_nst<CC, true>(), t);
-        turn_round_adj(it, a, lds, t);
+        turn_round_adj<B>(it, a, lds, t);
         // round r - 1: stages bits - LR - 1 .. 0, those below post_bits() on
         // the stored vectors
-        rounds<true, 0, post_bits()>(lds, it.bits - LR, t);
+        if constexpr (B > 0) rounds_ct<true, B - LR, 0, post_bits()>(lds, t);
+        else rounds<true, 0, post_bits()>(lds, bits - LR, t);
         store_contig<NT_INTER, C, post_bits()>(lds, static_cast<C *>(a.inter2),
-                                               a.inter2_is_io ? it.io_off : it.ws_off, it.bits,
+                                               a.inter2_is_io ? it.io_off : it.ws_off, bits,
                                                it.count, nullptr, t, C(1), false,
-                                               SignCtx{nullptr, 0, 0}, it.bits - LR);
+                                               SignCtx{nullptr, 0, 0}, bits - LR);
+    }
+
+    // Round-boundary tiles with block sizes known at compile time.  A tile
+    // of 2^CC rows has L1 = K - CC and blocks of 2^bits = 2^(m - L1) with
+    // 8 <= bits <= K (the plan check rejects others), so with 2^7 rows (the
+    // default split of signals of 2^16 .. 2^23) every block size has a form
+    // of its own; with 2^6 and 2^5 rows, the default splits' 2^15 (signals of
+    // 2^24 and 2^25) has one and other sizes take it at run time; 2^3 rows
+    // (forced splits only) take it at run time.
+    template <int CC>
+    static constexpr int turn_bits_lo() { return CC == CA ? 8 : (CC == CD || CC == CM) ? K : K + 1; }
+    template <int CC, int B = turn_bits_lo<CC>()>
+    static __device__ __forceinline__ void finish_turn_adj(const Item &it, const LaunchArgs &a,
+                                                           C *lds, int t)
+    {
+        if constexpr (B > K) {
+            finish_turn_adj_b<CC, 0>(it, a, lds, t);
+        } else if constexpr (B == K && CC == CA) {
+            finish_turn_adj_b<CC, K>(it, a, lds, t);  // bits 8 .. K - 1 taken above
+        } else {
+            if (it.bits == B) finish_turn_adj_b<CC, B>(it, a, lds, t);
+            else finish_turn_adj<CC, B + 1>(it, a, lds, t);
+        }
+    }
+    template <int CC, int B = turn_bits_lo<CC>()>
+    static __device__ __forceinline__ void finish_turn_bits(const Item &it, const LaunchArgs &a,
+                                                            C *lds, int t)
+    {
+        if constexpr (B > K) {
+            finish_turn_cc<CC, 0>(it, a, lds, t);
+        } else if constexpr (B == K && CC == CA) {
+            finish_turn_cc<CC, K>(it, a, lds, t);  // bits 8 .. K - 1 taken above
+        } else {
+            if (it.bits == B) finish_turn_cc<CC, B>(it, a, lds, t);
+            else finish_turn_bits<CC, B + 1>(it, a, lds, t);
+        }
     }
 
     static __device__ __forceinline__ void run_turn_adj(const Item &it, const LaunchArgs &a,
@@ -1443,10 +1487,10 @@ struct Engine {
     {
         if constexpr (K >= 15) {
             const int cc = K - (it.m - it.bits);
-            if (cc == CA) finish_turn_cc<CA>(it, a, lds, t);
-            else if (cc == CM) finish_turn_cc<CM>(it, a, lds, t);
-            else if (cc == CD) finish_turn_cc<CD>(it, a, lds, t);
-            else if (cc == CB) finish_turn_cc<CB>(it, a, lds, t);
+            if (cc == CA) finish_turn_bits<CA>(it, a, lds, t);
+            else if (cc == CM) finish_turn_bits<CM>(it, a, lds, t);
+            else if (cc == CD) finish_turn_bits<CD>(it, a, lds, t);
+            else if (cc == CB) finish_turn_bits<CB>(it, a, lds, t);
         }
     }
 
