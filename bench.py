@@ -33,6 +33,11 @@ METRIC = "CHW Gelem/s + % HBM peak, n=2^20 batch; plain FP32 vs BF16 ragged form
 HBM_PEAK_GBS = 8000.0
 PROFILE_HEADLINE = os.path.join(ROOT, "profiles", "chw_2p20_f32.md")
 PROFILE_RAGGED = os.path.join(ROOT, "profiles", "chw_ragged_bf16.md")
+# the rocprofv3 summary of each other workload's configuration line
+CONFIG_PROFILES = {name: os.path.join(ROOT, "profiles", f + ".md") for name, f in (
+    ("plain_small_f32", "chw_small_f32_64x2p10"), ("plain_small_i32", "chw_small_i32_64x2p10"),
+    ("plain_2p24_f32", "chw_2p24_f32"), ("precision_bf16", "chw_precision_bf16_8192x2p12"),
+    ("precision_f16", "chw_precision_f16_8192x2p12"), ("diff_f32", "chw_diff_f32_256x2p14"))}
 
 
 def log(*a):
@@ -630,11 +635,11 @@ def _copies(nbytes_per_set):
     return max(1, -(-ROTATE_BYTES // max(1, nbytes_per_set)))
 
 
-def _step_figures(elems, bpe, cold_ms, warm_ms, launches, ls):
+def _step_figures(elems, bpe, cold_ms, warm_ms, launches, ls, profile=None):
     return {"ms_per_step": round(cold_ms, 5), "warm_ms_per_step": round(warm_ms, 5),
             "Gelem_s": round(elems / (cold_ms / 1e3) / 1e9, 2),
             "warm_Gelem_s": round(elems / (warm_ms / 1e3) / 1e9, 2),
-            "roofline": roofline(bpe, launches, ls, None, elems)}
+            "roofline": roofline(bpe, launches, ls, profile, elems)}
 
 
 def bench_uniform_config(args, name, dev, stream):
@@ -670,10 +675,12 @@ def bench_uniform_config(args, name, dev, stream):
     warm_ms = time_steps(lambda: plan.forward(x0, out=y0, workspace=ws), steps, args.warmup, stream)
     launches = launch_breakdown(plan, cold, steps) if not args.no_launch_timing else [cold_ms]
     dt_code = {"f32": 0, "bf16": 1, "f16": 2, "i32": 3}[w.dtype]
+    splits = plan.describe()["plan"]["splits"]
     res = {"workload": w.note, "dtype": w.dtype, "elements": elems,
-           "copies_rotated": rot.copies, "splits": plan.describe()["plan"]["splits"]}
+           "copies_rotated": rot.copies, "splits": splits}
     res.update(_step_figures(elems, 2 * es, cold_ms, warm_ms, launches,
-                             plan_launches(plan, dt_code)))
+                             plan_launches(plan, dt_code),
+                             stored_profile(CONFIG_PROFILES[name], splits)))
     res["device_ms_per_step"] = round(float(sum(launches)), 5)
     res["forward_calls"] = (args.warmup + rot.copies + steps) + (args.warmup + steps) + \
         (0 if args.no_launch_timing else steps) + 1
@@ -767,7 +774,9 @@ def bench_diff_config(args, dev, stream):
     res = {"workload": w.note, "dtype": "f32", "elements": elems,
            "copies_rotated": rx.copies, "step": "forward + adjoint (fused signs)"}
     res.update(_step_figures(2 * elems, 8, cold_ms, warm_ms, launches,
-                             [dict(l, elements=elems) for l in ls]))
+                             [dict(l, elements=elems) for l in ls],
+                             stored_profile(CONFIG_PROFILES["diff_f32"],
+                                            plan.describe()["plan"]["splits"])))
     res["device_ms_per_step"] = round(float(sum(launches)), 5)
     res["unfused_ms_per_step"] = round(unf_ms, 5)
     # forward + adjoint pairs of this run (for per-step counter totals)

@@ -410,7 +410,9 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         if (r.persistent) {
             e = v->launch_persistent(dim3(looping_grid(ds, v->fn_persistent, v->nt, occ, a.nitems)),
                                      stream, a);
-        } else if (r.stream >= 1 && r.stream <= 5) {
+        } else if (r.stream > 0) {
+            // every prefetching launch runs its kernel or fails: no silent
+            // fallback to one workgroup per tile
             const bool dy = order == ORDER_DYADIC;
             const int slot = stream_slot(r.stream - 1);
             const void *fn = slot < 0 ? nullptr
@@ -419,8 +421,9 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
                                      : dy ? v->launch_stream[slot]
                                           : v->launch_stream_order[order - 1][slot];
             if (!fn || !lf)
-                return fail(CHW_ERR_UNSUPPORTED, "no prefetching kernel for %d-bit tiles in order %d",
-                            r.K, order);
+                return fail(CHW_ERR_UNSUPPORTED,
+                            "no prefetching kernel for %d-bit tiles of kind %d in order %d", r.K,
+                            r.stream - 1, order);
             e = lf(dim3(looping_grid(ds, fn, v->nt, occ, a.nitems)), stream, a);
         } else if (order != ORDER_DYADIC) {
             e = v->launch_order[order - 1](dim3(a.nitems), stream, a);

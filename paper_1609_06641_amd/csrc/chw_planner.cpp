@@ -542,12 +542,16 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         // 0.43 ms, 2^14 0.42 against 0.46, 2^13 0.42 against 0.47, and 1024
         // tiles of 2^14 signals 55 against 61 us; launches of a few hundred
         // tiles do better with one workgroup per tile); mode 2 prefetches in
-        // every launch that can
+        // every launch that can.  The forward first pass of 2^6-row tiles (2^24
+        // signals) runs one workgroup per tile in mode 1: 0.40 against 0.42 ms
+        // per 2^28 elements prefetching (2^7 rows: 0.38-0.39 either way; 2^5
+        // rows: 0.49 against 0.50, prefetching)
         auto form = [&](const LaunchRange &r, bool adj) {
             if (r.K != 15) return 0;
             const int s = stream_source(p.items, r.begin, r.end, r.K, adj);
             if (s == 1 + KIND_BLOCKS && p.cfg.stream == 1 && r.end - r.begin < kStreamBlocksMin)
                 return 0;
+            if (s == 1 + KIND_FIRST_D && !adj && p.cfg.stream == 1) return 0;
             return s;
         };
         // the adjoint of the other orders gathers by the order's map: one

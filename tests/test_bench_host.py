@@ -88,6 +88,22 @@ def test_profiles_name_their_kernels():
         assert bench.plan_launches(p, 0)[0]["symbol"] in f.read()
 
 
+def test_config_profiles_name_the_planned_kernels():
+    # every workload line's profile holds PMC bytes for each kernel its plan
+    # launches (a profile taken with other kernels cannot lend its traffic)
+    import workloads
+    for name, path in bench.CONFIG_PROFILES.items():
+        w = workloads.CONFIGS[name]
+        p = chw.Plan(w.log2_sizes * w.batch, dtype=w.dtype, norm=w.norm)
+        with open(path) as f:
+            summary = json.loads(f.read().split("```json\n")[1].split("\n```")[0])
+        dt = {"f32": 0, "bf16": 1, "f16": 2, "i32": 3}[w.dtype]
+        directions = ("forward", "backward") if name == "diff_f32" else ("forward",)
+        for direction in directions:
+            for launch in bench.plan_launches(p, dt, direction):
+                assert launch["symbol"] in summary["kernels_traffic_bytes"], (name, launch)
+
+
 def test_source_hash_ignores_comments():
     assert bench._code_only("a // x\n  b /* y\n z */ c\n") == "a b c"
     assert bench._code_only("int x = 1;  // one") == bench._code_only("int x = 1;\n")

@@ -176,6 +176,15 @@ def test_large_two_pass_sizes(m):
         assert gu.per_signal_rel(gu.host_f64(yf), ref_f, [m]).max() <= 1e-5, (m, l1)
         assert np.array_equal(gu.host_i64(yi), ref_i), (m, l1)
     assert all(t.equal(o, outs[-1]) for o in outs.values())
+    # the prefetching forms of every launch (the default leaves the 2^6-row
+    # first pass to one workgroup per tile)
+    p2 = chw.Plan([m], dtype="f32")
+    p2.set_option("stream", 2)
+    d = p2.describe()["plan"]
+    assert all(r["stream"] > 0 for r in d["forward"])
+    y2 = p2.forward(gu.dev_tensor(xf, "f32"))
+    _sync()
+    assert t.equal(y2, outs[-1])
     # the sequency order: the same values, rows listed by sign changes
     ps = chw.Plan([m], dtype="f32", order="sequency")
     ys = ps.forward(gu.dev_tensor(xf, "f32"))
