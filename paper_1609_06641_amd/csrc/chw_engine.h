@@ -1436,7 +1436,8 @@ struct Engine {
 
     // Round-boundary tiles with block sizes known at compile time.  A tile
     // of 2^CC rows has L1 = K - CC and blocks of 2^bits = 2^(m - L1) with
-    // 8 <= bits <= K (the plan check rejects others), so with 2^7 rows (the
+    // 8 <= bits <= K (the planner makes no other round-boundary tile, and the
+    // plan check rejects others), so with 2^7 rows (the
     // default split of signals of 2^16 .. 2^23) every block size has a form
     // of its own; with 2^6 and 2^5 rows, the default splits' 2^15 (signals of
     // 2^24 and 2^25) has one and other sizes take it at run time; 2^3 rows

@@ -267,9 +267,9 @@ def test_layout_selfcheck():
     # compiled 4-byte tile (16-byte vectors of 4 words, V = 4, or of 8 BF16 /
     # FP16 elements, V = 8) puts at most one word per bank into a half-wave
     # access; the FP64 tiles (V = 2, 8-byte words) at most two.  The
-    # transposed phase is compiled for 2^7 / 2^5 / 2^3 rows in 2^15 tiles and
-    # 2^6 / 2^4 / 2^3 rows in 2^12 tiles.
-    compiled_rows = {12: (6, 4, 3), 15: (7, 5, 3)}
+    # transposed phase is compiled for 2^7 / 2^6 / 2^5 / 2^3 rows in 2^15 tiles
+    # and 2^6 / 2^4 / 2^3 rows in 2^12 tiles.
+    compiled_rows = {12: (6, 4, 3), 15: (7, 6, 5, 3)}
     for r in rep:
         if "phase" not in r:
             continue
@@ -284,6 +284,7 @@ def test_layout_selfcheck():
 @pytest.mark.parametrize("opts", [dict(), dict(exec=2), dict(chunk=1 << 20), dict(single15=0),
                                   dict(split_l1=12), dict(exec=2, lr12=5), dict(stream=1),
                                   dict(stream=0), dict(stream=1, chunk=1 << 22, split_l1=8),
+                                  dict(stream=2), dict(split_l1=9), dict(split_l1=9, stream=2),
                                   dict(pipeline=1, chunk=1 << 20), dict(pipeline=1, chunk=1 << 23)])
 def test_plan_invariants_random_ragged(seed, opts):
     rng = np.random.default_rng(seed)
