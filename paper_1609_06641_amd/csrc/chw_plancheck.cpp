@@ -77,8 +77,10 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
                         *err = "single-pass tile larger than its kernel's tile";
                         return false;
                     }
-                } else if (it.kind == KIND_SIGNAL_A || it.kind == KIND_SIGNAL_B) {
-                    const int CC = it.kind == KIND_SIGNAL_A ? K12_CA : K12_CB;
+                } else if (is_signal_kind(it.kind)) {
+                    const int CC = it.kind == KIND_SIGNAL_A   ? K12_CA
+                                   : it.kind == KIND_SIGNAL_C ? K12_CM
+                                                              : K12_CB;
                     const int L1 = K - CC, b = it.m - L1;
                     if (!r.persistent || K != 12 || b < CC || b > K || it.bits != L1) {
                         *err = "whole-signal item with an invalid split";

@@ -50,8 +50,7 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
     int best_score = -1;
     for (const Opt &o : opts) {
         if (o.K1 == 15 && (dt == DT_F64 || k12_only)) continue;
-        if ((o.kind == KIND_FIRST_C || o.kind == KIND_FIRST_D) && k12_only)
-            continue;  // whole-signal items: A or B
+        if (o.kind == KIND_FIRST_D && k12_only) continue;  // whole-signal items: A, C or B
         const int L1 = o.K1 - o.CC;
         if (forced_l1 > 0 && L1 != forced_l1) continue;
         const int b = m - L1;                 // levels left for the second pass
@@ -392,7 +391,9 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
             for (const Item &f : ch.first[0]) {
                 if (f.h0 != 0) continue;  // one item per signal
                 Item it = blank_item();
-                it.kind = f.kind == KIND_FIRST_A ? KIND_SIGNAL_A : KIND_SIGNAL_B;
+                it.kind = f.kind == KIND_FIRST_A   ? KIND_SIGNAL_A
+                          : f.kind == KIND_FIRST_C ? KIND_SIGNAL_C
+                                                   : KIND_SIGNAL_B;
                 it.m = f.m;
                 it.bits = f.bits;          // L1
                 it.io_off = f.io_off;      // signal base (h0 = 0)
@@ -684,7 +685,7 @@ std::string describe_plan(const BuiltPlan &p)
         for (int k = r.begin; k < r.end; ++k) {
             const Item &it = p.items[k];
             if (it.kind == KIND_BLOCKS || it.kind == KIND_LAST) n += (int64_t)it.count << it.bits;
-            else if (it.kind == KIND_SIGNAL_A || it.kind == KIND_SIGNAL_B) n += (int64_t)1 << it.m;
+            else if (is_signal_kind(it.kind)) n += (int64_t)1 << it.m;
             else n += (int64_t)1 << r.K;  // first-pass and round-boundary tiles
         }
         return n;

@@ -39,7 +39,17 @@ enum ItemKind : int32_t {
     // runs): the split of 2^24 signals, whose blocks the 2^7-row tiles would
     // leave larger than a last-pass tile.
     KIND_FIRST_D = 8,
+    // Persistent launch: a whole multi-pass signal whose first-pass tiles
+    // have the middle row count (2^4 rows of 2^8 elements in 2^12-element
+    // tiles: 64-byte FP32 runs, against 32 with the 2^3 rows of
+    // KIND_SIGNAL_B), then its last-pass tiles, run by one workgroup.
+    KIND_SIGNAL_C = 9,
 };
+
+constexpr bool is_signal_kind(int kind)
+{
+    return kind == KIND_SIGNAL_A || kind == KIND_SIGNAL_B || kind == KIND_SIGNAL_C;
+}
 
 // Coefficient order of the transform's output (forward) / input (adjoint).
 // Dyadic (Paley) is the order of eq. (1); sequency (Walsh) lists the rows by
