@@ -372,10 +372,13 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *   "chunk"     elements of multi-pass signals per first/last pass pair
  *               (0 = the whole batch in one pair of launches)
  *   "exec"      0 = one launch per pass; 2 = one persistent launch in which a
- *               workgroup runs both passes of a multi-pass signal (2^12-element
- *               tiles; signals up to 2^21; also set by CHW_FLAG_PERSISTENT).
- *               1 (a dependency-counter work queue) is disabled: it gives
- *               CHW_ERR_UNSUPPORTED.
+ *               workgroup runs both passes of a multi-pass signal (also set by
+ *               CHW_FLAG_PERSISTENT).  1 (a dependency-counter work queue) is
+ *               disabled: it gives CHW_ERR_UNSUPPORTED.
+ *   "ptile"     tile size of the persistent launch: 12 (2^12-element tiles,
+ *               several workgroups per CU, signals up to 2^21), 15
+ *               (2^15-element tiles, one workgroup per CU, signals up to 2^23;
+ *               not FP64) or 0 (default: 15, and 12 for FP64).
  *   "pipeline"  1 (with "chunk" > 0): launch j runs the last pass of chunk
  *               j - 1 together with the first pass of chunk j, both in
  *               2^15-element tiles, and the chunks' intermediates alternate
@@ -459,7 +462,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
  *
  * chw_tuning_save writes every entry to the text file `path` (host string),
  * one line per key: the key, then name=value for each tuned option (lr12,
- * lr15, single15, split_l1, exec, chunk, stream, pipeline, spread,
+ * lr15, single15, split_l1, exec, ptile, chunk, stream, pipeline, spread,
  * occupancy); `comment` (may be NULL) is written first as '#' lines.
  * chw_tuning_load merges such a file into the cache: CHW_ERR_INVALID_ARGUMENT
  * (nothing merged, the line in chw_last_error) when it cannot be read or a

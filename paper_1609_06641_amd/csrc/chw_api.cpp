@@ -189,6 +189,7 @@ void copy_tunables(const PlanConfig &from, PlanConfig *to)
     to->single15 = from.single15;
     to->split_l1 = from.split_l1;
     to->exec = from.exec;
+    to->ptile = from.ptile;
     to->chunk = from.chunk;
     to->stream = from.stream;
     to->pipeline = from.pipeline;
@@ -208,6 +209,7 @@ const TunableField kTunables[] = {
     {"single15", 0, 1, nullptr, &PlanConfig::single15},
     {"split_l1", -1, 30, nullptr, &PlanConfig::split_l1},
     {"exec", 0, 2, nullptr, &PlanConfig::exec},
+    {"ptile", 0, 15, nullptr, &PlanConfig::ptile},
     {"chunk", 0, INT64_MAX, &PlanConfig::chunk, nullptr},
     {"stream", 0, 2, nullptr, &PlanConfig::stream},
     {"pipeline", 0, 1, nullptr, &PlanConfig::pipeline},
@@ -408,6 +410,9 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         hipError_t e;
         const int occ = b.cfg.occupancy;
         if (r.persistent) {
+            if (!v->launch_persistent || !v->fn_persistent)
+                return fail(CHW_ERR_UNSUPPORTED, "no persistent kernel for %d-bit tiles with %d registers",
+                            r.K, r.LR);
             e = v->launch_persistent(dim3(looping_grid(ds, v->fn_persistent, v->nt, occ, a.nitems)),
                                      stream, a);
         } else if (r.stream > 0) {
@@ -1136,6 +1141,7 @@ chw_status chw_plan_set_option(chw_plan_t plan, const char *key, int64_t value)
         return fail(CHW_ERR_UNSUPPORTED,
                     "exec 1 (dependency-counter work queue) is disabled");
     else if (k == "exec" && (value == 0 || value == 2)) cfg.exec = (int)value;
+    else if (k == "ptile" && (value == 0 || value == 12 || value == 15)) cfg.ptile = (int)value;
     else if (k == "chunk" && value >= 0) cfg.chunk = value;
     else if (k == "stream" && value >= 0 && value <= 2) cfg.stream = (int)value;
     else if (k == "pipeline" && (value == 0 || value == 1)) cfg.pipeline = (int)value;
@@ -1228,7 +1234,7 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             Split sp;
             bool ok = true;
             for (int32_t m : plan->m)
-                if (m > 15 && !choose_split(m, plan->dt, l1, false, plan->cfg.order, false, &sp)) ok = false;
+                if (m > 15 && !choose_split(m, plan->dt, l1, 0, plan->cfg.order, false, &sp)) ok = false;
             if (ok) l1s.push_back(l1);
         }
     if (!only_persistent) {
@@ -1265,15 +1271,17 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
             }
     }
     // the persistent launch computes the dyadic order only (the planner
-    // refuses it for the others) and takes signals up to 2^21
-    const bool can_persist = maxm <= 21 && plan->cfg.order == ORDER_DYADIC && !only_multi;
-    if (can_persist)
+    // refuses it for the others) and takes signals up to 2^21 in 2^12-element
+    // tiles, 2^23 in 2^15-element tiles (not FP64)
+    const bool can_persist = maxm <= 23 && plan->cfg.order == ORDER_DYADIC && !only_multi;
+    if (can_persist) {
         for (int lr12 : {5, 6})
             for (int occ : {0, 1, 2, 4}) {
-                if (plan->dt == DT_F64 && lr12 != 5) continue;
+                if (maxm > 21 || (plan->dt == DT_F64 && lr12 != 5)) continue;
                 PlanConfig c = plan->cfg;
                 c.lr12 = lr12;
                 c.exec = 2;
+                c.ptile = 12;
                 c.split_l1 = -1;
                 c.chunk = 0;
                 c.pipeline = 0;
@@ -1281,6 +1289,19 @@ chw_status chw_autotune(chw_plan_t plan, const void *x, void *y, void *workspace
                 c.occupancy = occ;
                 cands.push_back(c);
             }
+        if (plan->dt != DT_F64) {
+            PlanConfig c = plan->cfg;
+            c.lr15 = 5;
+            c.exec = 2;
+            c.ptile = 15;
+            c.split_l1 = -1;
+            c.chunk = 0;
+            c.pipeline = 0;
+            c.stream = 0;
+            c.occupancy = 0;
+            cands.push_back(c);
+        }
+    }
     // the plan's own configuration first: another one replaces the best so far
     // only when it is more than 1% faster, so near-ties keep the default and
     // repeated tunings pick the same kernels

@@ -78,11 +78,11 @@ bool check_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
                         return false;
                     }
                 } else if (is_signal_kind(it.kind)) {
-                    const int CC = it.kind == KIND_SIGNAL_A   ? K12_CA
-                                   : it.kind == KIND_SIGNAL_C ? K12_CM
-                                                              : K12_CB;
+                    const int CC = it.kind == KIND_SIGNAL_A   ? (K == 15 ? K15_CA : K12_CA)
+                                   : it.kind == KIND_SIGNAL_C ? mid_rows(K)
+                                                              : (K == 15 ? K15_CB : K12_CB);
                     const int L1 = K - CC, b = it.m - L1;
-                    if (!r.persistent || K != 12 || b < CC || b > K || it.bits != L1) {
+                    if (!r.persistent || (K != 12 && K != 15) || b < CC || b > K || it.bits != L1) {
                         *err = "whole-signal item with an invalid split";
                         return false;
                     }

@@ -31,9 +31,13 @@ int elem_bytes(int dt)
 
 int compute_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 
-bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool last15,
+bool choose_split(int m, int dt, int forced_l1, int whole, int order, bool last15,
                   Split *out)
 {
+    // whole = 12 / 15: both passes of the signal run in one workgroup of
+    // 2^whole-element tiles (the persistent launch); its first-pass kinds are
+    // the whole-signal ones (2^CA, 2^CM or 2^CB rows)
+    const bool k12_only = whole == 12, k15_only = whole == 15;
     struct Opt { int K1, CC, kind; };
     // preference: the widest transposed runs first (2^7 rows = 512-byte runs
     // of FP32 in the first pass's store)
@@ -42,6 +46,10 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
                         {12, K12_CM, KIND_FIRST_C}, {15, K15_CB, KIND_FIRST_B},
                         {12, K12_CB, KIND_FIRST_B}};
     const int kmax2 = (dt == DT_F64 || k12_only) ? 12 : 15;
+    if (k15_only) {
+        if (dt == DT_F64) return false;  // no FP64 2^15-element tiles
+        last15 = true;                  // the last pass runs in the same tile kernel
+    }
     // the natural order's last pass also stores runs, of 2^(K2 - b) blocks:
     // it takes the larger last-pass tile and the split whose shorter run is
     // longest; pipelined chunks run both passes in 2^15-element tiles
@@ -50,7 +58,8 @@ bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool l
     int best_score = -1;
     for (const Opt &o : opts) {
         if (o.K1 == 15 && (dt == DT_F64 || k12_only)) continue;
-        if (o.kind == KIND_FIRST_D && k12_only) continue;  // whole-signal items: A, C or B
+        if (o.K1 == 12 && k15_only) continue;
+        if (o.kind == KIND_FIRST_D && whole) continue;  // whole-signal items: A, C or B
         const int L1 = o.K1 - o.CC;
         if (forced_l1 > 0 && L1 != forced_l1) continue;
         const int b = m - L1;                 // levels left for the second pass
@@ -92,7 +101,7 @@ bool choose_split3(int m, int dt, Split3 *out)
         const int L1 = o.K1 - o.CC, b = m - L1;
         if (b < o.CC) continue;
         Split inner;
-        if (!choose_split(b, compute_dt(dt), -1, false, ORDER_DYADIC, false, &inner)) continue;
+        if (!choose_split(b, compute_dt(dt), -1, 0, ORDER_DYADIC, false, &inner)) continue;
         out->m = m;
         out->outer = Split{m, L1, o.K1, o.CC, o.kind, 0};
         out->inner = inner;
@@ -136,7 +145,18 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     const int64_t batch = (int64_t)ms.size();
     const int tiny_max = tiny_max_log2(dt);
     const bool persistent = p.cfg.exec == 2;
-    const int single_max = (p.cfg.single15 && !persistent) ? 15 : 12;
+    // the persistent launch runs one tile size for everything
+    // (measured on the ragged batch, 2^30 elements: BF16 2.60 ms in
+    // 2^15-element tiles against 3.26 ms in 2^12-element ones, FP32 3.17
+    // against 4.16 ms)
+    if (persistent && p.cfg.ptile == 15 && dt == DT_F64)
+        throw std::invalid_argument("no FP64 2^15-element tiles for the persistent launch");
+    const int ptile = !persistent              ? 0
+                      : p.cfg.ptile == 12      ? 12
+                      : p.cfg.ptile == 15      ? 15
+                      : dt == DT_F64           ? 12
+                                               : 15;
+    const int single_max = ptile ? ptile : (p.cfg.single15 ? 15 : 12);
     // signals that take three HBM passes: from 2^three_min in the dyadic
     // order; the other orders keep two passes up to 2^27 (the only sizes they
     // support)
@@ -185,7 +205,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     int per = 0;           // signals per tile in the current size group
     for (size_t s = 0; s < order.size();) {
         const int m = ms[order[s]];
-        const int K = m <= 12 ? 12 : 15;
+        const int K = ptile ? ptile : m <= 12 ? 12 : 15;
         if (s >= group_end) {
             // a launch of 2^15-element tiles (one workgroup fills a CU) that
             // would fill fewer tiles than there are CUs spreads its size groups
@@ -229,7 +249,7 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         if (three_pass(m)) continue;  // three passes, below
         Split sp;
         const bool pipe = p.cfg.pipeline && p.cfg.chunk > 0 && !persistent;
-        if (!choose_split(m, dt, p.cfg.split_l1, persistent, p.cfg.order, pipe, &sp))
+        if (!choose_split(m, dt, p.cfg.split_l1, ptile, p.cfg.order, pipe, &sp))
             throw std::invalid_argument("no two-pass split covers log2 size " +
                                         std::to_string(m));
         ++p.n_multi;
@@ -386,9 +406,9 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
     if (persistent) {
         // one launch; single-pass tiles and whole multi-pass signals, sorted by
         // decreasing work (the kernel hands items out grid-stride)
-        std::vector<Item> all(blocks[0]);
+        std::vector<Item> all(blocks[kidx(ptile)]);
         for (const Chunk &ch : chunks)
-            for (const Item &f : ch.first[0]) {
+            for (const Item &f : ch.first[kidx(ptile)]) {
                 if (f.h0 != 0) continue;  // one item per signal
                 Item it = blank_item();
                 it.kind = f.kind == KIND_FIRST_A   ? KIND_SIGNAL_A
@@ -408,8 +428,8 @@ void build_plan(const std::vector<int32_t> &ms, const std::vector<int64_t> &off,
         std::stable_sort(all.begin(), all.end(),
                          [&](const Item &x, const Item &y) { return work(x) > work(y); });
         LaunchRange r;
-        r.K = 12;
-        r.LR = p.cfg.lr12 ? p.cfg.lr12 : 6;
+        r.K = ptile;
+        r.LR = ptile == 15 ? 5 : p.cfg.lr12 ? p.cfg.lr12 : 6;  // compiled forms
         r.persistent = 1;
         r.begin = (int)p.items.size();
         p.items.insert(p.items.end(), all.begin(), all.end());
@@ -652,9 +672,9 @@ std::string describe_plan(const BuiltPlan &p)
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "\"config\": {\"lr12\": %d, \"lr15\": %d, \"single15\": %d, \"split_l1\": %d, "
-                  "\"exec\": %d, \"chunk\": %lld, \"stream\": %d, \"pipeline\": %d, \"order\": %d, "
-                  "\"turn\": %d, \"adjoint\": %d, \"spread\": %d, \"occupancy\": %d}, ",
-                  p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec,
+                  "\"exec\": %d, \"ptile\": %d, \"chunk\": %lld, \"stream\": %d, \"pipeline\": %d, "
+                  "\"order\": %d, \"turn\": %d, \"adjoint\": %d, \"spread\": %d, \"occupancy\": %d}, ",
+                  p.cfg.lr12, p.cfg.lr15, p.cfg.single15, p.cfg.split_l1, p.cfg.exec, p.cfg.ptile,
                   (long long)p.cfg.chunk, p.cfg.stream, p.cfg.pipeline, p.cfg.order, p.cfg.turn,
                   p.cfg.adjoint, p.cfg.spread, p.cfg.occupancy);
     s += buf;

@@ -21,8 +21,12 @@ struct PlanConfig {
     int single15 = 1;   // signals with 13 <= m <= 15 in one pass of a 2^15 tile
     int split_l1 = -1;  // forced first-pass level count of multi-pass signals
     int exec = 0;       // 0 = one launch per pass; 2 = one persistent launch
-                        // (2^12-element tiles, m <= 21; a workgroup runs both
-                        // passes of a multi-pass signal)
+                        // (a workgroup runs both passes of a multi-pass
+                        // signal)
+    int ptile = 0;      // tile bits of the persistent launch: 12 (m <= 21,
+                        // several workgroups per CU), 15 (m <= 23, one
+                        // workgroup per CU, 2^7-row first passes; not FP64)
+                        // or 0 = 15 where it exists, else 12
     int64_t chunk = 0;  // elements of multi-pass signals per pass pair (0 = all):
                         // the batch runs as first pass, last pass on each chunk
                         // in turn, so a chunk's intermediate can stay in the
@@ -161,7 +165,7 @@ int compute_bytes(int dt);
 
 // Choose the two-pass split for a signal of 2^m elements; false when none of
 // the compiled variants covers m.
-bool choose_split(int m, int dt, int forced_l1, bool k12_only, int order, bool last15,
+bool choose_split(int m, int dt, int forced_l1, int whole, int order, bool last15,
                   Split *out);
 
 // Choose the three-pass split of a dyadic-order signal of 2^m elements: the

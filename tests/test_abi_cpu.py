@@ -337,14 +337,35 @@ def test_dependency_queue_exec_is_disabled():
 
 
 def test_persistent_plan_shape():
+    # default (2^15-element tiles): 2 whole-signal items (20, 20), one tile
+    # for the single-pass 2^14 signal and one with the three 2^9 signals
     p = chw.Plan([20, 20, 14, 9, 9, 9], dtype="f32", persistent=True)
     d = p.describe()["plan"]
-    assert d["config"]["exec"] == 2
+    assert d["config"]["exec"] == 2 and d["config"]["ptile"] == 0
     assert len(d["forward"]) == 1 and d["forward"][0]["persistent"] == 1
+    assert d["forward"][0]["K"] == 15
     assert d["backward"] == d["forward"]
-    # 3 whole-signal items (20, 20, 14) + 1 tile with the three 2^9 signals
-    assert d["items"] == 4 and d["multi"] == 3
+    assert d["items"] == 4 and d["multi"] == 2
+    assert all(s["K1"] == 15 and s["K2"] == 15 and s["rows_log2"] == 7 for s in d["splits"])
     p.check()
+    # 2^12-element tiles: 3 whole-signal items (20, 20 with 2^4-row first
+    # passes, 14 with 2^6 rows) + 1 tile with the three 2^9 signals
+    q = chw.Plan([20, 20, 14, 9, 9, 9], dtype="f32", persistent=True)
+    q.set_option("ptile", 12)
+    d = q.describe()["plan"]
+    assert d["forward"][0]["K"] == 12
+    assert d["items"] == 4 and d["multi"] == 3
+    assert sorted((s["m"], s["rows_log2"]) for s in d["splits"]) == [(14, 6), (20, 4)]
+    q.check()
+    # signals of 2^22 and 2^23 only in 2^15-element tiles; FP64 only in 2^12
+    r = chw.Plan([23, 22, 5], dtype="bf16", persistent=True)
+    r.check()
+    with pytest.raises(chw.CHWError):
+        r.set_option("ptile", 12)
+    f = chw.Plan([20, 9], dtype="f64", persistent=True)
+    assert f.describe()["plan"]["forward"][0]["K"] == 12
+    with pytest.raises(chw.CHWError):
+        f.set_option("ptile", 15)
 
 
 def test_stream_plan_shape():
@@ -669,7 +690,7 @@ def test_tuning_cache_roundtrip(tmp_path):
     key = p0.describe()["tuning_key"]
     assert p0.describe()["tuned"] == 0
     f = tmp_path / "t.txt"
-    f.write_text("# comment\n\n%s lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 "
+    f.write_text("# comment\n\n%s lr12=5 lr15=6 single15=1 split_l1=10 exec=0 ptile=0 chunk=0 "
                  "stream=0 pipeline=0 spread=1 occupancy=3\n" % key)
     chw.tuning_load(str(f))
     assert chw.tuning_count() == 1
@@ -702,10 +723,10 @@ def test_tuning_cache_roundtrip(tmp_path):
 
 @pytest.mark.parametrize("line", [
     "k lr12=5",                                                  # options missing
-    "k lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=99",
-    "k lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=1 bogus=1",
-    "k lr12=5 lr12=5 lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1",
-    "k lr12=x lr15=6 single15=1 split_l1=10 exec=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=1",
+    "k lr12=5 lr15=6 single15=1 split_l1=10 exec=0 ptile=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=99",
+    "k lr12=5 lr15=6 single15=1 split_l1=10 exec=0 ptile=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=1 bogus=1",
+    "k lr12=5 lr12=5 lr15=6 single15=1 split_l1=10 exec=0 ptile=0 chunk=0 stream=0 pipeline=0 spread=1",
+    "k lr12=x lr15=6 single15=1 split_l1=10 exec=0 ptile=0 chunk=0 stream=0 pipeline=0 spread=1 occupancy=1",
     "k lr12= lr15=6",
     "k =5",
 ])

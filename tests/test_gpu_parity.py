@@ -553,11 +553,16 @@ def test_streams_concurrent():
 # ---------------------------------------------------------------------------
 # one persistent launch (ragged batches), with graph replay
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16", "i32", "f64"])
-def test_persistent_ragged(dtype):
+@pytest.mark.parametrize("dtype,ptile", [("f32", 12), ("bf16", 12), ("i32", 12), ("f64", 12),
+                                         ("f32", 15), ("bf16", 15), ("i32", 15)])
+def test_persistent_ragged(dtype, ptile):
+    # one workgroup per whole multi-pass signal, in 2^12- or 2^15-element
+    # tiles (2^22 and 2^23 signals in the latter only)
     rng = np.random.default_rng(1234)
     ms = rng.integers(3, 21 if dtype != "f64" else 17, size=60).astype(np.int32)
     ms[:4] = [12, 13, 16, 20] if dtype != "f64" else [12, 13, 16, 14]
+    if ptile == 15:
+        ms[4:6] = [23, 22]
     offs = workloads.packed_offsets(ms)
     total = int(offs[-1])
     norm = "none" if dtype == "i32" else "ortho"
@@ -568,9 +573,11 @@ def test_persistent_ragged(dtype):
     plain = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs)
     for graph in (False, True):
         p = chw.Plan(ms, dtype=dtype, norm=norm, offsets=offs, persistent=True, graph=graph)
+        p.set_option("ptile", ptile)
         p.set_option("adjoint", 1)
         d = p.describe()["plan"]
         assert len(d["forward"]) == 1 and d["forward"][0]["persistent"] == 1
+        assert d["forward"][0]["K"] == ptile
         xd = gu.dev_tensor(x, dtype)
         ws = gu.torch().empty(max(p.workspace_size(), 16), dtype=gu.torch().uint8, device="cuda")
         outs = []
