@@ -161,10 +161,10 @@ def roofline(bytes_per_elem, launches_ms, launches, profile, total_elems):
     }
 
 
-# Planner options when neither --plan-config nor the tuning file gives them:
-# the planner's own choices for the uniform batches; for the ragged form one
-# launch per pass replayed as a graph with 2^5 registers in the 2^12-element
-# tiles (the tuning file's entry for the ragged workload).
+# Planner options for --plan-config-less runs that bypass the tuning file: the
+# planner's own choices for the uniform batches; for the ragged form one
+# launch per pass replayed as a graph with 2^5 registers.  (The ragged leg
+# itself starts from TUNING_FILE, see tuned_ragged_plan.)
 BENCH_CONFIG = {"plan": {},
                 "ragged": {"exec": 0, "lr12": 5, "lr15": 5, "single15": 1, "split_l1": -1,
                            "stream": 1}}
@@ -369,6 +369,22 @@ def bench_forms(args, x, y, m, batch, stream):
 # ragged plans from it (the tuning cache), so that every run times the kernels
 # the stored profiles name.  Without the file the run autotunes live.
 TUNING_FILE = os.path.join(ROOT, "paper_1609_06641_amd", "tuning_gfx950.txt")
+
+
+def tuned_ragged_plan(ks, offs, dtype, persistent=False):
+    """The ragged workload's plan in the configuration the benchmark times:
+    graph-replayed, starting from TUNING_FILE's entry (the cache is emptied
+    again afterwards); raises when the file holds no entry for it."""
+    from paper_1609_06641_amd import chw
+    chw.tuning_clear()
+    chw.tuning_load(TUNING_FILE)
+    try:
+        p = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=persistent)
+    finally:
+        chw.tuning_clear()
+    if not p.describe()["tuned"]:
+        raise RuntimeError("no entry for the ragged %s plan in %s" % (dtype, TUNING_FILE))
+    return p
 
 
 def ragged_inputs(dtype, dev):

@@ -104,6 +104,22 @@ def test_config_profiles_name_the_planned_kernels():
                 assert launch["symbol"] in summary["kernels_traffic_bytes"], (name, launch)
 
 
+def test_tuning_file_holds_the_ragged_plans():
+    # the committed tuning file has an entry for each ragged plan the
+    # benchmark times (four launches and one launch, BF16 and FP32), and
+    # loading it leaves the cache empty again
+    import workloads
+    ks = workloads.ragged_log2_sizes(4001)
+    offs = workloads.packed_offsets(ks)
+    for dtype in ("bf16", "f32"):
+        for persistent in (False, True):
+            p = bench.tuned_ragged_plan(ks, offs, dtype, persistent=persistent)
+            c = p.describe()["plan"]["config"]
+            assert c["exec"] == (2 if persistent else 0)
+            p.check()
+    assert chw.tuning_count() == 0
+
+
 def test_source_hash_ignores_comments():
     assert bench._code_only("a // x\n  b /* y\n z */ c\n") == "a b c"
     assert bench._code_only("int x = 1;  // one") == bench._code_only("int x = 1;\n")

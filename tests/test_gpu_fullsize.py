@@ -141,9 +141,7 @@ def test_ragged_full_bench_config(dtype):
     # the launch configuration the benchmark times for the ragged form
     torch = gu.torch()
     ks, offs, xt = _ragged_inputs(dtype)
-    plan = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=True)
-    for k, v in bench.BENCH_CONFIG["ragged"].items():
-        plan.set_option(k, v)
+    plan = bench.tuned_ragged_plan(ks, offs, dtype)
     ws = torch.empty(max(plan.workspace_size(), 16), dtype=torch.uint8, device="cuda")
     y = plan.forward(xt, workspace=ws)
     torch.cuda.synchronize()

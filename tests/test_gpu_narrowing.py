@@ -123,11 +123,8 @@ def test_ragged_bf16_bench_form_rne():
     ks = workloads.ragged_log2_sizes(4001)
     offs = workloads.packed_offsets(ks)
     xb = workloads.to_half_precision(workloads.ragged_values(4002, ks, offs), "bf16").cuda()
-    p_h = chw.Plan(ks, dtype="bf16", offsets=offs, graph=True, persistent=True)
-    p_f = chw.Plan(ks, dtype="f32", offsets=offs, persistent=True)
-    for p in (p_h, p_f):
-        for k, v in bench.BENCH_CONFIG["ragged"].items():
-            p.set_option(k, v)
+    p_h = bench.tuned_ragged_plan(ks, offs, "bf16")
+    p_f = bench.tuned_ragged_plan(ks, offs, "f32")
     ws = torch.empty(max(p_h.workspace_size(), 16), dtype=torch.uint8, device="cuda")
     yh = p_h.forward(xb, workspace=ws)
     torch.cuda.synchronize()
