@@ -145,7 +145,7 @@ def roofline(bytes_per_elem, launches_ms, launches, profile, total_elems):
     return {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": per_kernel.get(dom_l["symbol"]) if profile else None,
+        "traffic": per_kernel.get(dom_l.get("key", dom_l["symbol"])) if profile else None,
         "kernel": dom_l["name"],
         "algorithmic_bytes_per_launch": algo_dom,
         "units_per_launch": dom_l["elements"], "bytes_per_unit": bytes_per_elem,
@@ -213,7 +213,24 @@ def plan_launches(plan, dt_code, direction="forward"):
                 dt_code, r["K"], r["LR"], ca, adj, order)
         out.append({"name": "%s items [%d,%d)" % (name, r["begin"], r["end"]),
                     "elements": r["elements"], "symbol": sym})
+    for l, k in zip(out, launch_keys(out)):
+        l["key"] = k
     return out
+
+
+def launch_keys(launches):
+    """Profile key of each launch of a call: its kernel symbol, with "#j" for
+    the j-th launch of a symbol the call launches more than once (the
+    summaries keep those launches apart by their order within the call)."""
+    count, seen, keys = {}, {}, []
+    for l in launches:
+        count[l["symbol"]] = count.get(l["symbol"], 0) + 1
+    for l in launches:
+        s = l["symbol"]
+        j = seen.get(s, 0)
+        seen[s] = j + 1
+        keys.append(s if s is None or count[s] == 1 else "%s#%d" % (s, j))
+    return keys
 
 
 def launch_names(plan, direction="forward"):
@@ -412,14 +429,14 @@ def write_tuning(args, dev, stream):
         for persistent in (False, True):
             p = chw.Plan(ks, dtype=dtype, offsets=offs, graph=True, persistent=persistent)
             ws = torch.empty(max(p.workspace_size(), 16), dtype=torch.uint8, device=dev)
-            p.autotune(xb, yb, workspace=ws, iters=5)
+            p.autotune(xb, yb, workspace=ws, iters=20)
             log("tuned %s persistent=%d: %s" % (dtype, persistent, p.describe()["plan"]["config"]))
             p.close()
             del ws
         del xb, yb
         torch.cuda.empty_cache()
     comment = ("autotuner results for the ragged workload (20000 signals, 2^30 elements; BF16 "
-               "and FP32; all launch forms and the persistent one), 5 timed calls per candidate\n"
+               "and FP32; all launch forms and the persistent one), 20 timed calls per candidate\n"
                "written by: python3 bench.py --write-tuning (%s, %s)"
                % (torch.cuda.get_device_properties(0).gcnArchName, torch.cuda.get_device_name(0)))
     chw.tuning_save(TUNING_FILE, comment)
@@ -921,17 +938,40 @@ def summarize(args):
              "repository root, P an output folder):", ""]
     for c in args.cmd or []:
         lines.append("    " + c)
+    bj = {}
+    if args.bench_json and os.path.exists(args.bench_json):
+        with open(args.bench_json) as f:
+            bj = json.loads(f.read().strip().splitlines()[-1])
+    trace_calls = bj.get("forward_calls")
+
+    def per_launch(vals, calls):
+        """A kernel's dispatches split by launch position within a call (one
+        list when the call launches it once or the count does not divide)."""
+        n = len(vals)
+        q = n // calls if calls and n % calls == 0 and n // calls > 1 else 1
+        return [vals[j::q] for j in range(q)]
+
+    def label(k, j, parts):
+        return "`%s`" % k[:90] if parts == 1 else "`%s` #%d" % (k[:90], j)
     if stats:
-        lines += ["", "| kernel | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
+        lines += ["", "| kernel (#j: its j-th launch in a call) | dispatches | avg us | min us | max us |",
+                  "|---|---|---|---|---|"]
     for k, v in stats.items():
         if "chw::" in k or "copyBuffer" in k:
-            lines.append("| `%s` | %d | %.1f | %.1f | %.1f |" % (k[:90], len(v), sum(v) / len(v), min(v), max(v)))
+            parts = per_launch(v, trace_calls if "chw::" in k else None)
+            for j, vj in enumerate(parts):
+                lines.append("| %s | %d | %.1f | %.1f | %.1f |" % (label(k, j, len(parts)), len(vj),
+                                                                 sum(vj) / len(vj), min(vj), max(vj)))
     if fetch:
         lines += ["", "| kernel | dispatches | FETCH_SIZE KiB avg | WRITE_SIZE KiB avg |", "|---|---|---|---|"]
     for k in fetch:
         if "chw::" in k or "copyBuffer" in k:
-            lines.append("| `%s` | %d | %.0f | %.0f |" % (k[:90], len(fetch[k]), sum(fetch[k]) / len(fetch[k]),
-                                                         sum(write.get(k, [0])) / max(1, len(write.get(k, [0])))))
+            wk = write.get(k, [0])
+            fparts = per_launch(fetch[k], args.calls if "chw::" in k and len(wk) == len(fetch[k]) else None)
+            wparts = per_launch(wk, args.calls) if len(fparts) > 1 else [wk]
+            for j, (fj, wj) in enumerate(zip(fparts, wparts)):
+                lines.append("| %s | %d | %.0f | %.0f |" % (label(k, j, len(fparts)), len(fj),
+                                                           sum(fj) / len(fj), sum(wj) / max(1, len(wj))))
     counters = {}
     if args.counters:
         con = _db(args.counters)
@@ -950,23 +990,31 @@ def summarize(args):
             for k, d in counters.items():
                 act, bc = d["SQ_LDS_IDX_ACTIVE"], d["SQ_LDS_BANK_CONFLICT"]
                 lines.append("* `%s`: %.3f" % (k, bc / max(1.0, act - bc)))
-    splits = None
-    if args.bench_json and os.path.exists(args.bench_json):
-        with open(args.bench_json) as f:
-            bj = json.loads(f.read().strip().splitlines()[-1])
-        splits = bj.get("config", {}).get("splits", bj.get("splits"))
+    splits = bj.get("config", {}).get("splits", bj.get("splits")) if bj else None
     per_kernel = {}
     if ff and fw:
         for k in fetch:
             if "chw::" in k and write.get(k):
-                per_kernel[k[:90]] = int((sum(fetch[k]) / len(fetch[k]) * ff +
-                                          sum(write[k]) / len(write[k]) * fw) * 1024)
+                # a kernel launched q > 1 times per call: one entry per launch
+                # position within the call ("#j"), from every q-th dispatch
+                n = len(fetch[k])
+                q = n // args.calls if args.calls and n % args.calls == 0 and \
+                    len(write[k]) == n else 1
+                for j in range(q):
+                    fj, wj = fetch[k][j::q], write[k][j::q]
+                    key = k[:90] if q == 1 else "%s#%d" % (k[:90], j)
+                    per_kernel[key] = int((sum(fj) / len(fj) * ff + sum(wj) / len(wj) * fw) * 1024)
     summary = {"source_hash": kernel_source_hash(), "calls": args.calls, "splits": splits,
                "fetch_factor": ff, "write_factor": fw,
                "traffic_bytes_per_transform": traffic,
                "kernels_traffic_bytes": per_kernel,
-               "kernels_avg_us": {k[:90]: round(sum(v) / len(v), 2) for k, v in stats.items()
-                                  if "chw::" in k}}
+               "kernels_avg_us": {}}
+    for k, v in stats.items():
+        if "chw::" in k:
+            parts = per_launch(v, trace_calls)
+            for j, vj in enumerate(parts):
+                key = k[:90] if len(parts) == 1 else "%s#%d" % (k[:90], j)
+                summary["kernels_avg_us"][key] = round(sum(vj) / len(vj), 2)
     if counters:
         summary["counters"] = counters
     lines += ["", "Machine-readable summary (the benchmark reports `traffic` from it while",

@@ -101,7 +101,20 @@ def test_config_profiles_name_the_planned_kernels():
         directions = ("forward", "backward") if name == "diff_f32" else ("forward",)
         for direction in directions:
             for launch in bench.plan_launches(p, dt, direction):
-                assert launch["symbol"] in summary["kernels_traffic_bytes"], (name, launch)
+                assert launch["key"] in summary["kernels_traffic_bytes"], (name, launch)
+
+
+def test_launch_keys_number_repeated_kernels():
+    ls = [{"symbol": "a"}, {"symbol": "b"}, {"symbol": "a"}, {"symbol": None}]
+    assert bench.launch_keys(ls) == ["a#0", "b", "a#1", None]
+    # the ragged BF16 profile keys each launch of the tuned plan
+    import workloads
+    ks = workloads.ragged_log2_sizes(4001)
+    p = bench.tuned_ragged_plan(ks, workloads.packed_offsets(ks), "bf16")
+    with open(bench.PROFILE_RAGGED) as f:
+        summary = json.loads(f.read().split("```json\n")[1].split("\n```")[0])
+    for launch in bench.plan_launches(p, 1):
+        assert launch["key"] in summary["kernels_traffic_bytes"], launch
 
 
 def test_tuning_file_holds_the_ragged_plans():
