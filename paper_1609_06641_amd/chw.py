@@ -86,6 +86,14 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libchw.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # torch ships its own HIP runtime under the same soname; loaded
+        # first, it is the one libchw binds to, so the process has a single
+        # runtime (loaded after libchw's, torch would map a second one, which
+        # then sees no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -19,6 +19,7 @@ CHOICES = {
     "split_l1": (-1, 6, 8, 9, 10, 12),
     "stream": (0, 1, 2),
     "exec": (0, 2),
+    "ptile": (0, 12, 15),
     "chunk": (0, 1 << 20),
     "pipeline": (0, 1),
     "adjoint": (0, 1),
