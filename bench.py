@@ -32,7 +32,8 @@ if ROOT not in sys.path:
 METRIC = "CHW Gelem/s + % HBM peak, n=2^20 batch; plain FP32 vs BF16 ragged form"
 HBM_PEAK_GBS = 8000.0
 PROFILE_HEADLINE = os.path.join(ROOT, "profiles", "chw_2p20_f32.md")
-PROFILE_RAGGED = os.path.join(ROOT, "profiles", "chw_ragged_bf16.md")
+# the ragged workload's summary per storage type
+PROFILE_RAGGED = {dt: os.path.join(ROOT, "profiles", "chw_ragged_%s.md" % dt) for dt in ("bf16", "f32")}
 # the rocprofv3 summary of each other workload's configuration line
 CONFIG_PROFILES = {name: os.path.join(ROOT, "profiles", f + ".md") for name, f in (
     ("plain_small_f32", "chw_small_f32_64x2p10"), ("plain_small_i32", "chw_small_i32_64x2p10"),
@@ -487,7 +488,7 @@ def bench_ragged(args, dev, stream, dtype):
         rels.append(float(metrics.rel_l2(yb[o:o + n].double().cpu().numpy(), ref)))
     d = rp.describe()["plan"]
     dt_code = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
-    profile = stored_profile(PROFILE_RAGGED, d["splits"]) if dtype == "bf16" else None
+    profile = stored_profile(PROFILE_RAGGED[dtype], d["splits"])
     res = {"value": round(relems / (rms / 1e3) / 1e9, 3), "unit": "Gelem/s",
            "ms_per_step": round(rms, 4), "signals": len(ks), "elements": relems,
            "dtype": "%s storage, fp32 compute" % dtype if dtype != "f32" else "f32",

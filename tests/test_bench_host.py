@@ -75,7 +75,7 @@ def test_every_configuration_names_its_launches():
 def test_profiles_name_their_kernels():
     # the committed summaries carry per-kernel PMC bytes keyed by the symbols
     # plan_launches derives
-    for path in (bench.PROFILE_HEADLINE, bench.PROFILE_RAGGED):
+    for path in (bench.PROFILE_HEADLINE, *bench.PROFILE_RAGGED.values()):
         with open(path) as f:
             text = f.read()
         summary = json.loads(text.split("```json\n")[1].split("\n```")[0])
@@ -107,14 +107,15 @@ def test_config_profiles_name_the_planned_kernels():
 def test_launch_keys_number_repeated_kernels():
     ls = [{"symbol": "a"}, {"symbol": "b"}, {"symbol": "a"}, {"symbol": None}]
     assert bench.launch_keys(ls) == ["a#0", "b", "a#1", None]
-    # the ragged BF16 profile keys each launch of the tuned plan
+    # each ragged profile keys every launch of its tuned plan
     import workloads
     ks = workloads.ragged_log2_sizes(4001)
-    p = bench.tuned_ragged_plan(ks, workloads.packed_offsets(ks), "bf16")
-    with open(bench.PROFILE_RAGGED) as f:
-        summary = json.loads(f.read().split("```json\n")[1].split("\n```")[0])
-    for launch in bench.plan_launches(p, 1):
-        assert launch["key"] in summary["kernels_traffic_bytes"], launch
+    for dtype, code in (("bf16", 1), ("f32", 0)):
+        p = bench.tuned_ragged_plan(ks, workloads.packed_offsets(ks), dtype)
+        with open(bench.PROFILE_RAGGED[dtype]) as f:
+            summary = json.loads(f.read().split("```json\n")[1].split("\n```")[0])
+        for launch in bench.plan_launches(p, code):
+            assert launch["key"] in summary["kernels_traffic_bytes"], (dtype, launch)
 
 
 def test_tuning_file_holds_the_ragged_plans():
