@@ -357,6 +357,11 @@ def bench_forms(args, x, y, m, batch, stream):
         "y = H D_3 H D_2 H D_1 x, one shared diagonal per round; each round's last pass and "
         "the next round's first pass run as one launch")
     res["signed_3_rounds"]["launches_per_call"] = k + 1 if p.describe()["plan"]["turn"] else 2 * k
+    rec("signed_3_rounds_adjoint", p,
+        lambda: p.backward_signed(x, signs, "shared", k, out=y, workspace=ws),
+        "x = D_1 H D_2 H D_3 H g through the forward launches (the Paley-ordered H is "
+        "symmetric): diagonals shifted by a round, D_1 at the last pass's store")
+    res["signed_3_rounds_adjoint"]["launches_per_call"] = res["signed_3_rounds"]["launches_per_call"]
     # one round with a fresh per-element diagonal drawn on the device every call
     pe_words = torch.empty(p.sign_words("per_element"), dtype=torch.int32, device=x.device)
     seed = [0]

@@ -326,7 +326,12 @@ chw_status chw_nodes_workspace_size(chw_plan_t plan, size_t *bytes);
 /* chw_backward_signed -- the adjoint of chw_forward_signed:
  *     y_i = D_1 H^T D_2 H^T ... D_k H^T g_i
  * (rounds in reverse order, each diagonal applied to its round's output as
- * it is stored).  Same arguments and rules as chw_forward_signed. */
+ * it is stored).  A dyadic-order plan whose multi-round calls use
+ * round-boundary tiles runs its two-pass signals through the forward launches
+ * (H^T = H with the same bits, see chw_backward): round 1 without a diagonal,
+ * D_k .. D_2 at the boundaries, D_1 at the last pass's store; option
+ * "adjoint" = 1 runs the synthesis kernels instead.  Same arguments and rules
+ * as chw_forward_signed. */
 chw_status chw_backward_signed(chw_plan_t plan, const void *g, void *y, void *workspace,
                                const uint32_t *signs, chw_sign_mode mode, int rounds,
                                void *stream);
@@ -400,9 +405,10 @@ chw_status chw_plan_destroy(chw_plan_t plan);
  *   "spread"    1 (default): a launch of single-pass 2^15-element tiles that
  *               would fill fewer than 256 tiles puts its signals one or a few
  *               per tile (partly filled tiles, more CUs busy); 0: packed.
- *   "adjoint"   0 (default): chw_backward of a dyadic-order plan runs the
- *               forward launches (same bits, see chw_backward); 1: the Haar
- *               synthesis kernels.
+ *   "adjoint"   0 (default): chw_backward of a dyadic-order plan, and the
+ *               two-pass signals of a multi-round chw_backward_signed with
+ *               round-boundary tiles, run the forward launches (same bits,
+ *               see chw_backward); 1: the Haar synthesis kernels.
  *   "occupancy" 0 (default): the looping launches (the persistent kernel,
  *               the prefetching kernels) run as many workgroups as can be
  *               resident; 1 .. 32: at most that many per CU (grid = min(items,

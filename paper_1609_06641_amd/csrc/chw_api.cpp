@@ -339,10 +339,13 @@ chw_status mark(chw_plan_t p, DeviceState &ds, int i, hipStream_t stream)
 // the call's previous ones unless `fresh`.
 // `phase` selects launches: 0 all; 1 the tiny kernel, single-pass launches
 // and the pass a two-pass signal starts with (forward: first pass; adjoint:
-// last pass); 2 the pass it ends with.
+// last pass); 2 the pass it ends with; 3 the tiny kernel and single-pass
+// launches only; 4 the starting passes of two-pass signals only.
+// `last_signed` (forward, phase 2): the last pass applies the iteration's
+// diagonal to its output at the store.
 chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y, void *inter,
                    int inter_is_io, hipStream_t stream, const SignArgs &sg = SignArgs{},
-                   int ri = 0, bool fresh = true, int phase = 0)
+                   int ri = 0, bool fresh = true, int phase = 0, bool last_signed = false)
 {
     const BuiltPlan &b = p->built;
     chw_status ms;
@@ -369,7 +372,7 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
     // the other orders run one launch per round for every launch
     const int order = b.cfg.order;
     const bool fuse = order == ORDER_DYADIC;
-    if (!b.tiny_off.empty() && (ri == 0 || !fuse) && phase != 2) {
+    if (!b.tiny_off.empty() && (ri == 0 || !fuse) && phase != 2 && phase != 4) {
         const TinyVariant *tv = find_tiny_variant(p->dt, adj);
         if (!tv) return fail(CHW_ERR_UNSUPPORTED, "no tiny kernel for this dtype");
         const int n = (int)b.tiny_off.size();
@@ -385,7 +388,8 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         if (phase != 0) {
             const int kind = b.items[r.begin].kind;
             const bool start = r.single_pass || (adj ? kind == KIND_LAST : is_first_kind(kind));
-            if ((phase == 1) != start) continue;
+            if ((phase != 2) != start) continue;
+            if ((phase == 3 && !r.single_pass) || (phase == 4 && r.single_pass)) continue;
         }
         a.signs = in_launch_rounds ? sg.w : w_round;
         a.rounds = in_launch_rounds ? k : 1;
@@ -409,7 +413,12 @@ chw_status enqueue(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *
         a.nitems = r.end - r.begin;
         hipError_t e;
         const int occ = b.cfg.occupancy;
-        if (r.persistent) {
+        if (last_signed) {
+            if (!v->launch_last_signed)
+                return fail(CHW_ERR_UNSUPPORTED, "no last-pass kernel with a store-side diagonal "
+                            "for %d-bit tiles", r.K);
+            e = v->launch_last_signed(dim3(a.nitems), stream, a);
+        } else if (r.persistent) {
             if (!v->launch_persistent || !v->fn_persistent)
                 return fail(CHW_ERR_UNSUPPORTED, "no persistent kernel for %d-bit tiles with %d registers",
                             r.K, r.LR);
@@ -509,11 +518,45 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int s
 // signals instead of 2k.  The adjoint does the same backwards: round k - 1's
 // adjoint last pass, boundaries that end round r and start round r - 1, and
 // round 0's adjoint first pass.
+// A signed adjoint of a dyadic plan with round-boundary tiles can run the
+// forward launches: the Paley-ordered matrix is symmetric and its adjoint
+// cascade performs the forward's additions in the forward's order, so
+// D_1 H D_2 H ... D_k H g has the same bits either way.  Run forward, the
+// chain is round 0 without a diagonal, boundary i applying D_{k+1-i}, and
+// the last pass's output times D_1 -- its boundaries read their intermediate
+// contiguously and write runs, where the adjoint's gather strided runs.
+// Needs a store-side kernel for every last-pass launch and no persistent one;
+// option "adjoint" keeps the synthesis kernels.
+static bool adjoint_by_forward(chw_plan_t p)
+{
+    const BuiltPlan &b = p->built;
+    if (b.cfg.order != ORDER_DYADIC || b.cfg.adjoint) return false;
+    for (const LaunchRange &r : b.fwd) {
+        if (r.persistent) return false;
+        if (r.single_pass || b.items[r.begin].kind != KIND_LAST) continue;
+        const ItemsVariant *v = find_items_variant(p->dt, r.K, r.LR, 0);
+        if (!v || !v->launch_last_signed) return false;
+    }
+    return true;
+}
+
 chw_status enqueue_rounds(chw_plan_t p, DeviceState &ds, int adj, const void *x, void *y,
                           void *ws, void *inter0, int inter_is_io0, hipStream_t stream,
                           const SignArgs &sg)
 {
     const int k = sg.w ? sg.rounds : 1;
+    if (k > 1 && !p->built.turn.empty() && ws && adj && adjoint_by_forward(p)) {
+        // single-pass work through the synthesis kernels (every round inside
+        // the launch), then the forward chain of the two-pass signals; its
+        // buffers alternate as in the forward call below
+        auto buf = [&](int i) { return i % 2 != 0 ? y : ws; };
+        chw_status s = enqueue(p, ds, 1, x, y, buf(0), 0, stream, sg, 0, true, 3);
+        if (s == CHW_OK) s = enqueue(p, ds, 0, x, y, buf(0), 0, stream, SignArgs{}, 0, false, 4);
+        for (int i = 1; i < k && s == CHW_OK; ++i)
+            s = enqueue_turn(p, ds, 0, buf(i - 1), (i - 1) % 2, buf(i), i % 2, y, stream, sg, k - i);
+        if (s != CHW_OK) return s;
+        return enqueue(p, ds, 0, y, y, buf(k - 1), (k - 1) % 2, stream, sg, 0, false, 2, true);
+    }
     if (k > 1 && !p->built.turn.empty() && ws) {
         // Intermediates 0 .. k-1 of the chain take turns between the workspace
         // and y.  A pass that reads transposed runs from all over a signal

@@ -644,12 +644,15 @@ struct Engine {
 
     // Memory position (blk << bits) | p holds tile element (blk << bits) |
     // bitrev_bits(p): the dyadic order of eq. (1) is the natural radix-2 order
-    // read at bit-reversed positions.
-    template <bool H, typename T>
+    // read at bit-reversed positions.  SG: the output also takes the diagonal
+    // sg after the scale (position o of the tile is buffer element off + o,
+    // signal position sg.jbase + o; no block list).
+    template <bool H, typename T, bool SG = false>
     static __device__ __forceinline__ void store_paley(const C *lds, T *dst, int64_t off,
                                                        int bits, int count,
                                                        const int64_t *list, int t,
-                                                       C scale, bool do_scale)
+                                                       C scale, bool do_scale,
+                                                       const SignCtx &sg = SignCtx{nullptr, 0, 0})
     {
         constexpr int V = Vec<T>::V, NV = N / (V * NT);
         if (bits == K) {
@@ -662,6 +665,12 @@ struct Engine {
                 for (int u = 0; u < V; ++u) {
                     vals[u] = lb[L::pad((int)cbrev((uint32_t)(V * NT * k + u), K))];
                     if (do_scale) vals[u] = scale_mul(vals[u], scale);
+                }
+                if constexpr (SG) {
+                    const int o = V * t + V * NT * k;
+                    const uint32_t w = sign_bits(sg, off + o, o);
+#pragma unroll
+                    for (int u = 0; u < V; ++u) vals[u] = apply_sign(vals[u], (w >> u) & 1u);
                 }
                 vstore<H>(d + V * NT * k, vals);
             }
@@ -685,6 +694,11 @@ struct Engine {
                         if (do_scale) vals[u] = scale_mul(vals[u], scale);
                     }
                     const int64_t g = list ? list[blk] + p0 : off + o0;
+                    if constexpr (SG) {
+                        const uint32_t w = sign_bits(sg, g, o0);
+#pragma unroll
+                        for (int u = 0; u < V; ++u) vals[u] = apply_sign(vals[u], (w >> u) & 1u);
+                    }
                     vstore<H>(dst + g, vals);
                 }
             }
@@ -1493,6 +1507,22 @@ struct Engine {
             else if (cc == CD) finish_turn_bits<CD>(it, a, lds, t);
             else if (cc == CB) finish_turn_bits<CB>(it, a, lds, t);
         }
+    }
+
+    // A forward last-pass tile whose output takes the diagonal a.signs at the
+    // store, after the scale: the last launch of a signed adjoint run through
+    // the forward launches (D_1 H D_2 H ... D_k H g, the last H's output
+    // times D_1).  One workgroup per tile.
+    static __device__ __forceinline__ void last_signed(const Item &it, const LaunchArgs &a,
+                                                       C *lds, int t)
+    {
+        load_contig<NT_INTER, C>(lds, static_cast<const C *>(a.inter), last_base(it, a), it.bits,
+                                 it.count, nullptr, t);
+        __syncthreads();
+        rounds<false>(lds, it.bits, t);
+        store_paley<NT_OUT, S, true>(lds, static_cast<S *>(a.out), it.io_off, it.bits, it.count,
+                                     nullptr, t, ortho_scale<C>(it.m), a.ortho != 0,
+                                     SignCtx{a.signs, it.io_off - it.sig_off, a.sign_shared});
     }
 
     template <bool ADJ, int ORD = ORDER_DYADIC>

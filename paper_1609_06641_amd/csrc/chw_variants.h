@@ -35,6 +35,8 @@ struct ItemsVariant {
     const void *fn_turn_stream;
     ItemsLauncher launch_turn_adj_stream[4];  // prefetching adjoint form per
     const void *fn_turn_adj_stream[4];        // row count: 2^CA, 2^CM, 2^CB, 2^CD
+    ItemsLauncher launch_last_signed; // forward last-pass tiles with a diagonal
+                                      // at the store, one workgroup per tile
 };
 
 struct TinyVariant {

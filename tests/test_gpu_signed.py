@@ -228,33 +228,37 @@ def test_signed_persistent_and_split_forms(dtype):
                          ids=["rows7-5", "rows3"])
 def test_round_boundary_tiles_bitwise(dtype, mode, sizes, split):
     # signed multi-round calls join round r's last pass and round r + 1's
-    # first pass (KIND_TURN tiles; the adjoint the other way round): the same
-    # bits as one launch pair per round, with and without prefetching, in place
-    # and out of place; every compiled first-pass row count (m = 16, 20, 21:
-    # 2^7 rows; 24: 2^6; 25: 2^5; a forced first pass of 12 levels: 2^3)
+    # first pass (KIND_TURN tiles): the same bits as one launch pair per round,
+    # with and without prefetching, in place and out of place; every compiled
+    # first-pass row count (m = 16, 20, 21: 2^7 rows; 24: 2^6; 25: 2^5; a
+    # forced first pass of 12 levels: 2^3).  The adjoint runs the forward
+    # launches (diagonals shifted by a round, the last one at the last pass's
+    # store) or, with option adjoint, the synthesis boundary tiles; the
+    # reference plan's adjoint runs the synthesis kernels one round at a time.
     t = gu.torch()
     norm = "none" if dtype == "i32" else "ortho"
     gen = workloads.int_signals if dtype == "i32" else workloads.float_signals
     x = np.concatenate([gen(760 + i, 1, k)[0] for i, k in enumerate(sizes)])
     xd = gu.dev_tensor(x, dtype)
     plans = {}
-    for turn, stream in ((0, 1), (1, 1), (1, 0)):
+    for turn, stream, adjoint in ((0, 1, 0), (1, 1, 0), (1, 0, 0), (1, 1, 1)):
         p = chw.Plan(sizes, dtype=dtype, norm=norm)
         p.set_option("turn", turn)
         p.set_option("stream", stream)
+        p.set_option("adjoint", adjoint)
         if split > 0:
             p.set_option("split_l1", split)
-        plans[(turn, stream)] = p
-    ref_plan = plans[(0, 1)]
+        plans[(turn, stream, adjoint)] = p
+    ref_plan = plans[(0, 1, 0)]
     assert ref_plan.describe()["plan"]["turn"] == []
-    assert plans[(1, 1)].describe()["plan"]["turn"]
+    assert plans[(1, 1, 0)].describe()["plan"]["turn"]
     nbits = (1 << max(sizes)) if mode == "shared" else ref_plan.extent
     ws = t.empty(max(ref_plan.workspace_size(), 16), dtype=t.uint8, device="cuda")
     for rounds in (2, 3, 4):
         s = _signs_dev(workloads.pack_sign_bits(workloads.sign_rounds(770 + rounds, rounds, nbits)))
         want = ref_plan.forward_signed(xd, s, mode, rounds, workspace=ws)
         want_b = ref_plan.backward_signed(xd, s, mode, rounds, workspace=ws)
-        for key in ((1, 1), (1, 0)):
+        for key in ((1, 1, 0), (1, 0, 0), (1, 1, 1)):
             got = plans[key].forward_signed(xd, s, mode, rounds, workspace=ws)
             got_b = plans[key].backward_signed(xd, s, mode, rounds, workspace=ws)
             inplace = xd.clone()
