@@ -326,12 +326,12 @@ chw_status chw_nodes_workspace_size(chw_plan_t plan, size_t *bytes);
 /* chw_backward_signed -- the adjoint of chw_forward_signed:
  *     y_i = D_1 H^T D_2 H^T ... D_k H^T g_i
  * (rounds in reverse order, each diagonal applied to its round's output as
- * it is stored).  A dyadic-order plan whose multi-round calls use
- * round-boundary tiles runs its two-pass signals through the forward launches
- * (H^T = H with the same bits, see chw_backward): round 1 without a diagonal,
- * D_k .. D_2 at the boundaries, D_1 at the last pass's store; option
- * "adjoint" = 1 runs the synthesis kernels instead.  Same arguments and rules
- * as chw_forward_signed. */
+ * it is stored).  A dyadic-order plan runs its two-pass signals through the
+ * forward launches (H^T = H with the same bits, see chw_backward) in one-round
+ * calls, and in multi-round calls where it uses round-boundary tiles: round 1
+ * without a diagonal, D_k .. D_2 at the boundaries, D_1 at the last pass's
+ * store; option "adjoint" = 1 runs the synthesis kernels instead.  Same
+ * arguments and rules as chw_forward_signed. */
 chw_status chw_backward_signed(chw_plan_t plan, const void *g, void *y, void *workspace,
                                const uint32_t *signs, chw_sign_mode mode, int rounds,
                                void *stream);

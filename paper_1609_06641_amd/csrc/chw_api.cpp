@@ -525,12 +525,13 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int s
 // chain is round 0 without a diagonal, boundary i applying D_{k+1-i}, and
 // the last pass's output times D_1 -- its boundaries read their intermediate
 // contiguously and write runs, where the adjoint's gather strided runs.
-// Needs a store-side kernel for every last-pass launch and no persistent one;
-// option "adjoint" keeps the synthesis kernels.
+// Needs a store-side kernel for every last-pass launch, no persistent launch
+// and no three-pass signal; option "adjoint" keeps the synthesis kernels.  A
+// one-round call needs no boundary: first pass, then the last pass with D_1.
 static bool adjoint_by_forward(chw_plan_t p)
 {
     const BuiltPlan &b = p->built;
-    if (b.cfg.order != ORDER_DYADIC || b.cfg.adjoint) return false;
+    if (b.cfg.order != ORDER_DYADIC || b.cfg.adjoint || b.n_three > 0) return false;
     for (const LaunchRange &r : b.fwd) {
         if (r.persistent) return false;
         if (r.single_pass || b.items[r.begin].kind != KIND_LAST) continue;
@@ -545,7 +546,7 @@ chw_status enqueue_rounds(chw_plan_t p, DeviceState &ds, int adj, const void *x,
                           const SignArgs &sg)
 {
     const int k = sg.w ? sg.rounds : 1;
-    if (k > 1 && !p->built.turn.empty() && ws && adj && adjoint_by_forward(p)) {
+    if (sg.w && (k == 1 || !p->built.turn.empty()) && ws && adj && adjoint_by_forward(p)) {
         // single-pass work through the synthesis kernels (every round inside
         // the launch), then the forward chain of the two-pass signals; its
         // buffers alternate as in the forward call below

@@ -3,6 +3,7 @@
 #include "chw_kernels.inc"
 
 CHW_INST_ITEMS(chw::DT_F64, 12, 5, CHW_K12_CA, 3)
+template __global__ void chw::chw_last_signed_kernel<chw::DT_F64, 12, 5, CHW_K12_CA, 3>(chw::LaunchArgs);
 CHW_INST_PERSIST(chw::DT_F64, 5)
 CHW_INST_TINY(chw::DT_F64)
 CHW_INST_HAAR(chw::DT_F64)

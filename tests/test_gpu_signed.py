@@ -254,7 +254,7 @@ def test_round_boundary_tiles_bitwise(dtype, mode, sizes, split):
     assert plans[(1, 1, 0)].describe()["plan"]["turn"]
     nbits = (1 << max(sizes)) if mode == "shared" else ref_plan.extent
     ws = t.empty(max(ref_plan.workspace_size(), 16), dtype=t.uint8, device="cuda")
-    for rounds in (2, 3, 4):
+    for rounds in (1, 2, 3, 4):
         s = _signs_dev(workloads.pack_sign_bits(workloads.sign_rounds(770 + rounds, rounds, nbits)))
         want = ref_plan.forward_signed(xd, s, mode, rounds, workspace=ws)
         want_b = ref_plan.backward_signed(xd, s, mode, rounds, workspace=ws)
