@@ -518,8 +518,8 @@ chw_status enqueue_turn(chw_plan_t p, DeviceState &ds, int adj, void *src, int s
 // signals instead of 2k.  The adjoint does the same backwards: round k - 1's
 // adjoint last pass, boundaries that end round r and start round r - 1, and
 // round 0's adjoint first pass.
-// A signed adjoint of a dyadic plan with round-boundary tiles can run the
-// forward launches: the Paley-ordered matrix is symmetric and its adjoint
+// A signed adjoint of a dyadic plan (one round, or several with round-boundary
+// tiles) can run the forward launches: the Paley-ordered matrix is symmetric and its adjoint
 // cascade performs the forward's additions in the forward's order, so
 // D_1 H D_2 H ... D_k H g has the same bits either way.  Run forward, the
 // chain is round 0 without a diagonal, boundary i applying D_{k+1-i}, and
