@@ -804,3 +804,19 @@ def test_other_orders_keep_two_passes_to_2p27():
             assert p.workspace_size() == 4 << m
         with pytest.raises(chw.CHWError):
             chw.Plan([28], order=order)
+
+
+def test_library_loads_after_torch():
+    # torch's HIP runtime carries the same soname as the system one; libchw
+    # binds to whichever the process loaded first, so loading it must bring
+    # torch in first (else torch would map a second runtime that sees no
+    # device).  Checked in a fresh interpreter.
+    import subprocess
+    import sys
+    code = ("import sys; from paper_1609_06641_amd import chw; "
+            "assert 'torch' not in sys.modules; chw.load(); "
+            "assert 'torch' in sys.modules; print('ok')")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=300)
+    assert res.returncode == 0 and res.stdout.strip().endswith("ok"), res.stderr[-2000:]
